@@ -448,13 +448,25 @@ void orc_sub(const orc_params *P, const uint64_t *a, const uint64_t *b, uint64_t
       }
 }
 
+/* Residue-wise product by the integer K (any integer-valued double). */
+static void mul_by_integer(const orc_params *P, const uint64_t *a, int level, double K, uint64_t *out) {
+  const int N = 1 << P->log_n;
+  for (int poly = 0; poly < 2; poly++)
+    for (int i = 0; i < level; i++) {
+      const uint64_t k = residue_dbl(K, P->q[i]);
+      for (int j = 0; j < N; j++) {
+        size_t o = ((size_t)poly * level + i) * N + j;
+        out[o] = mulmod(a[o], k, P->q[i]);
+      }
+    }
+}
+
 /* Multiply by a plaintext constant c.  An integer-valued c multiplies exactly
- * and keeps the scale; any other c is represented as
- * K = rint(c * q_{level-1}) at scale * q_{level-1}, so that a following rescale
- * (division by q_{level-1}) restores the scale (Sec. 2.2.3, rescaling). */
+ * and keeps the scale; any other c is represented as K = rint(c * q_{level-1}) at
+ * scale * q_{level-1}, so that a following rescale (division by q_{level-1})
+ * restores the scale (Sec. 2.2.3, rescaling). */
 int orc_mul_const(const orc_params *P, const uint64_t *a, int level, double scale, double c, uint64_t *out,
                   double *out_scale) {
-  const int N = 1 << P->log_n;
   double K;
   double new_scale = scale;
   if (c == rint(c)) {
@@ -464,14 +476,7 @@ int orc_mul_const(const orc_params *P, const uint64_t *a, int level, double scal
     new_scale = scale * (double)P->q[level - 1];
   }
   if (!isfinite(K)) return -1;
-  for (int poly = 0; poly < 2; poly++)
-    for (int i = 0; i < level; i++) {
-      const uint64_t k = residue_dbl(K, P->q[i]);
-      for (int j = 0; j < N; j++) {
-        size_t o = ((size_t)poly * level + i) * N + j;
-        out[o] = mulmod(a[o], k, P->q[i]);
-      }
-    }
+  mul_by_integer(P, a, level, K, out);
   if (out_scale) *out_scale = new_scale;
   return 0;
 }
@@ -618,7 +623,7 @@ void orc_value_encrypt(const orc_params *P, const uint64_t *pk, const uint64_t *
 /* ------------------------------------------------------------------------ */
 /* mean filter (Sec. 4.4.1): I'(y,x) = (1/k^2) sum over the k x k window,    */
 /* borders clamped to the edge; the ciphertext sum is followed by a          */
-/* multiplication by 1/k^2 and a rescale.                                    */
+/* multiplication by 1/k^2 (scaled by the last prime) and a rescale.         */
 /* ------------------------------------------------------------------------ */
 int orc_mean_filter_pixel(const orc_params *P, const uint64_t *img, int H, int W, int level, double scale,
                           int k, int y, int x, uint64_t *out, double *out_scale) {
@@ -634,9 +639,11 @@ int orc_mean_filter_pixel(const orc_params *P, const uint64_t *img, int H, int W
       xx = xx < 0 ? 0 : (xx >= W ? W - 1 : xx);
       orc_add(P, acc, img + ((size_t)yy * W + xx) * S, acc, level);
     }
-  double s1;
-  int rc = orc_mul_const(P, acc, level, scale, 1.0 / (double)(k * k), tmp, &s1);
-  if (rc == 0) rc = orc_rescale(P, tmp, level, s1, out, out_scale);
+  /* the factor 1/k^2 always takes the scaled representation rint(q_{level-1} / k^2) at
+   * scale * q_{level-1}, so the rescale restores the scale for every k (also k = 1) */
+  const double ql = (double)P->q[level - 1];
+  mul_by_integer(P, acc, level, rint((1.0 / (double)(k * k)) * ql), tmp);
+  int rc = orc_rescale(P, tmp, level, scale * ql, out, out_scale);
   free(acc);
   free(tmp);
   return rc;
