@@ -1,0 +1,246 @@
+/*
+ * ckks_mi355x.h -- C ABI of the MI355X (gfx950) pixel-level CKKS library.
+ *
+ * Implements the data-parallel path of iCHEETAH (arXiv 2409.03568): per-pixel
+ * CKKS encryption (Sec. 2.2.2), the cached encryption of Sec. 3.2 with the
+ * randomness of Sec. 3.3, the homomorphic operations of Sec. 2.2.3 and the pixel
+ * operations of Sec. 4.4 (mean filter, brightness), and decryption.
+ *
+ * General conventions
+ *  - Every function returns an int status: CKKS_OK (0) or a negative CKKS_E*
+ *    code; ckks_last_error() returns a thread-local message for the last failure.
+ *    No C++ exception crosses this boundary.
+ *  - Pointers whose name starts with d_ (and the data field of ckks_ct_batch) are
+ *    DEVICE pointers on the context's GPU; host_ pointers are host memory.
+ *  - Ownership: the caller owns every pixel, ciphertext and output buffer; the
+ *    library owns the context, keys, tables and caches (freed by *_destroy).  No
+ *    caller pointer is kept after the enqueued work has completed.
+ *  - Asynchrony: compute calls validate their arguments synchronously, then
+ *    enqueue on `stream` (a hipStream_t; NULL = the null stream) and return.
+ *    Calls on different streams may run concurrently once keys and caches exist;
+ *    two calls writing the same buffer must be ordered by the caller.
+ *  - Ciphertext layout (coefficient domain, canonical residues in [0, q_i)):
+ *      data[ct][poly 0..1][limb 0..level-1][coefficient 0..N-1], uint64.
+ *    A batch shares one level and one scale.
+ *  - Determinism: ciphertext t of an encryption call equals the result for pixel
+ *    index first_index + t computed alone, bit for bit, whatever the batch size,
+ *    stream or tiling: all randomness comes from Philox4x64-10 (Salmon et al.,
+ *    SC'11) keyed by the 2-word seed with counter (index, tag, block, 0).
+ */
+#ifndef CKKS_MI355X_H
+#define CKKS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define CKKS_OK 0
+#define CKKS_EINVAL (-1)        /* bad argument (null pointer, size, unsupported value) */
+#define CKKS_ENOMEM (-2)        /* device allocation failed */
+#define CKKS_ENOMEM_BUDGET (-3) /* request larger than a configured byte budget */
+#define CKKS_EDEVICE (-4)       /* HIP runtime error (launch, copy, earlier asynchronous fault) */
+#define CKKS_ELEVEL (-5)        /* operand levels differ, or level too low for the operation */
+#define CKKS_ESCALE (-6)        /* operand scales differ */
+#define CKKS_ECACHE (-7)        /* cache kind / descriptor mismatch, or pixel not representable */
+#define CKKS_EUNSUPPORTED (-8)  /* parameter outside what the kernels implement */
+#define CKKS_ESTATE (-9)        /* keys not generated or imported yet */
+
+typedef struct ckks_ctx ckks_ctx;
+typedef struct ckks_cache ckks_cache;
+
+/* CKKS parameters (Sec. 2.2, Table 1: ring dimension N, modulus Q, scale Delta;
+ * Sec. 4.2 uses N = 2^12, Q ~ 2^109 and a ternary secret).
+ *  log_n       N = 2^log_n; the kernels implement 11 <= log_n <= 14.
+ *  num_primes  L, the number of RNS primes (1..16); Q = q_0 ... q_{L-1}.
+ *  prime_bits  every q_i has exactly this many bits, 20 <= prime_bits <= 50
+ *              (the modular arithmetic is exact FP64, which needs q < 2^50).
+ *  log_scale   Delta = 2^log_scale.  Pixel coefficients must stay below q_{L-1}/2:
+ *              256 * 2^(log_scale + 1 - log_n) < q_{L-1} is required.
+ *  sigma       standard deviation of the discrete Gaussian errors (0 = no noise).
+ *  gauss_bound tail cut B of the Gaussian; 0 selects floor(6 sigma).  B <= 64.
+ *  primes      NULL selects the L largest primes below 2^prime_bits that are
+ *              1 mod 2N, in descending order; otherwise L caller-chosen primes
+ *              (each 1 mod 2N, exactly prime_bits bits, distinct), copied.      */
+typedef struct ckks_params {
+  uint32_t log_n;
+  uint32_t num_primes;
+  uint32_t prime_bits;
+  uint32_t log_scale;
+  double sigma;
+  uint32_t gauss_bound;
+  uint32_t reserved;
+  const uint64_t *primes;
+} ckks_params;
+
+/* A batch of ciphertexts: data is a device pointer to count * ckks_ct_bytes(level) bytes. */
+typedef struct ckks_ct_batch {
+  uint64_t *data;
+  uint64_t count;
+  uint32_t level;
+  uint32_t reserved;
+  double scale;
+} ckks_ct_batch;
+
+/* Cache kinds of Sec. 3.2. */
+#define CKKS_CACHE_RADIX 1      /* Enc(0) and Enc(r^i), i < digits; pixels combined from base-r digits */
+#define CKKS_CACHE_VALUE_TOPK 2 /* scanning-based: the topk most frequent values of a scan image */
+#define CKKS_CACHE_VALUE_FULL 3 /* full caching: Enc(v) for every v in 0..255 */
+
+/* base, digits: radix caches (2 <= base <= 256, base^digits >= 256, base^(digits-1) <= 255).
+ * topk:        VALUE_TOPK (1..256).
+ * zero_pool:   VALUE_* caches: size n of the pool of encrypted zeros added to every cached
+ *              pixel (Sec. 3.3 randomness pool), 1..4096.                                  */
+typedef struct ckks_cache_desc {
+  int32_t kind;
+  uint32_t base;
+  uint32_t digits;
+  uint32_t topk;
+  uint32_t zero_pool;
+} ckks_cache_desc;
+
+/* ---- host-only queries (no GPU needed) ---- */
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *ckks_last_error(void);
+
+/* Resolve a parameter set without touching the GPU: writes the L primes that a
+ * context would use to host_primes[L] and the Gaussian bound actually used to
+ * *gauss_bound (either may be NULL).  Errors: CKKS_EINVAL, CKKS_EUNSUPPORTED. */
+int ckks_params_resolve(const ckks_params *params, uint64_t *host_primes, uint32_t *gauss_bound);
+
+/* Host tables a context would upload, for inspection:
+ *   ckks_host_cdt_table: 2B cumulative thresholds of the Gaussian (Sec. 2.2.1 error
+ *     distribution; sample = -B + #{k : w >= T[k]} for a Philox word w) -> host_out[2B];
+ *   ckks_host_encode_table: T_j = 2^(log_scale+1-log_n) cos(pi j / N), j < N, the
+ *     closed-form inverse embedding of a pixel placed in slot 0 (Sec. 2.2) -> host_out[N]. */
+int ckks_host_cdt_table(const ckks_params *params, uint64_t *host_out, uint32_t capacity);
+int ckks_host_encode_table(const ckks_params *params, double *host_out, uint64_t capacity);
+
+/* ---- context ---- */
+
+/* Create a context on HIP device `device`: computes primes, roots of unity, NTT
+ * twiddles and the encoding / Gaussian tables and uploads them.  *out receives the
+ * context (owned by the library).  Errors: CKKS_EINVAL, CKKS_EUNSUPPORTED,
+ * CKKS_ENOMEM, CKKS_EDEVICE. */
+int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out);
+/* Wait for all work of the context and free it.  NULL is ignored. */
+void ckks_context_destroy(ckks_ctx *ctx);
+
+/* Bytes of one ciphertext at `level` (2 * level * N * 8); 0 for a bad level. */
+uint64_t ckks_ct_bytes(const ckks_ctx *ctx, uint32_t level);
+/* Context parameters: N, L, Delta and the primes (host_primes[L], may be NULL). */
+int ckks_context_info(const ckks_ctx *ctx, uint32_t *log_n, uint32_t *num_primes, double *scale,
+                      uint64_t *host_primes);
+
+/* ---- keys (Sec. 2.2.2, key generation steps 1-2) ---- */
+
+/* Generate s (ternary), e (Gaussian), a_i (uniform mod q_i) from Philox keyed by seed
+ * (counter index 0; tags 16, 17, 32+i) and set pk = (-a*s + e, a), on the GPU.
+ * Synchronous: returns after the keys are ready.  No evaluation key is generated
+ * (no ciphertext-ciphertext product is implemented). */
+int ckks_keygen(ckks_ctx *ctx, const uint64_t seed[2]);
+/* Copy the keys out: host_s[N] (int64 in {-1,0,1}), host_pk[2][L][N]. Either may be NULL. */
+int ckks_keys_export(ckks_ctx *ctx, int64_t *host_s, uint64_t *host_pk);
+/* Install keys produced elsewhere (s[N] in {-1,0,1}; pk[2][L][N] canonical residues). */
+int ckks_keys_import(ckks_ctx *ctx, const int64_t *host_s, const uint64_t *host_pk);
+
+/* ---- encryption ---- */
+
+/* Plain per-pixel encryption (Sec. 2.2.2): for t < n, with v ternary and e0, e1
+ * Gaussian drawn from Philox keyed by seed at counter index first_index + t (tags 1,
+ * 2, 3), and m the slot-0 encoding of pixel d_px[t] at scale Delta:
+ *   c0 = v*pk0 + e0 + m,  c1 = v*pk1 + e1   (mod q_i, every limb).
+ * out->data must hold n ciphertexts of level L; on success out->count = n,
+ * out->level = L, out->scale = Delta.  n = 0 is a no-op. */
+int ckks_encrypt_pixels(ckks_ctx *ctx, const uint8_t *d_px, uint64_t n, const uint64_t seed[2],
+                        uint64_t first_index, ckks_ct_batch *out, void *stream);
+
+/* Build a cache (Sec. 3.2) under cache_seed:
+ *  RADIX:      entries Enc(0) (index 0) and Enc(base^i) (index 1+i), i < digits;
+ *  VALUE_TOPK: histogram of d_scan[n_scan] on the GPU, the topk most frequent values
+ *              (count descending, value ascending, only values that occur), each
+ *              Enc(v) at index 256+v;
+ *  VALUE_FULL: Enc(v) at index 256+v for all 256 values (d_scan ignored);
+ *  VALUE_*:    a pool of zero_pool encrypted zeros, member u at index 512+u.
+ * Entries are plain encryptions exactly as ckks_encrypt_pixels computes them.  The
+ * call enqueues on `stream`; the cache is usable by later work on the same stream
+ * (synchronize before using it on another stream).  *out owns the device memory. */
+int ckks_cache_build(ckks_ctx *ctx, const ckks_cache_desc *desc, const uint8_t *d_scan, uint64_t n_scan,
+                     const uint64_t cache_seed[2], ckks_cache **out, void *stream);
+void ckks_cache_destroy(ckks_cache *cache);
+/* Number of cached value entries (RADIX: digits + 1; VALUE_FULL: 256; VALUE_TOPK: the
+ * number of distinct values kept, which waits for the build on the stream). */
+int ckks_cache_entries(ckks_cache *cache, uint32_t *n_entries);
+/* Copy a built cache to host memory (waits for the build).  host_values[n] receives the
+ * plaintext value of each entry and host_entries[n][2][L][N] the entries, n as reported by
+ * ckks_cache_entries (RADIX: entry 0 is Enc(0), entry 1+i is Enc(base^i)); host_pool
+ * receives the zero_pool encrypted zeros of a value cache.  Any pointer may be NULL. */
+int ckks_cache_export(ckks_cache *cache, uint32_t *host_values, uint64_t *host_entries, uint64_t *host_pool);
+
+/* Cached encryption of pixel d_px[t], index first_index + t, under the job seed:
+ *  RADIX (Sec. 3.2 + 3.3): c = Enc(0) + sum_i d_i Enc(base^i) over the base-`base`
+ *    digits d_i of the pixel, then for i = 1..digits-1, if bit i-1 of auxiliary
+ *    Philox word 1 (tag 4) is set, c += Enc(base^i) - base * Enc(base^(i-1)).
+ *  VALUE_* (Sec. 3.2 + 3.3): a cached value p gives c = Enc(p) + Z_u with
+ *    u = floor(zero_pool * w / 2^64), w = auxiliary word 0; a value that is not
+ *    cached is encrypted in full exactly like ckks_encrypt_pixels.
+ * Output as for ckks_encrypt_pixels.  Uses temporary device memory (stream-ordered). */
+int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
+                        const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream);
+
+/* ---- homomorphic operations (Sec. 2.2.3) ---- */
+
+/* out = a + b (ckks_add) or a - b (ckks_sub), residue-wise.  a and b must have the
+ * same count and level (CKKS_ELEVEL) and exactly equal scales (CKKS_ESCALE).  out->data
+ * may alias a->data or b->data; out->count/level/scale are set. */
+int ckks_add(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream);
+int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream);
+
+/* out = c * a.  An integer-valued c multiplies exactly and keeps the scale; any other c
+ * multiplies by K = rint(c * q_{level-1}) and sets out->scale = a->scale * q_{level-1}, so
+ * that ckks_rescale restores the scale.  out->data may alias a->data. */
+int ckks_mul_const(ckks_ctx *ctx, const ckks_ct_batch *a, double c, ckks_ct_batch *out, void *stream);
+
+/* In place: add the plaintext b, encoded like a pixel (slot 0) at the batch's scale,
+ * m_j = rint(((b * scale) * 2^(1-log_n)) * cos(pi j / N)), to c0 of every ciphertext.
+ * d_b (nullable) gives one b per ciphertext; otherwise the scalar b is used.
+ * Brightness (Sec. 4.4.2) and the watermark (Sec. 4.4.4). */
+int ckks_add_const(ckks_ctx *ctx, ckks_ct_batch *a, const double *d_b, double b, void *stream);
+
+/* Rescale (Sec. 2.2.3): divide by q = q_{level-1} with rounding, floor((x + floor(q/2)) / q),
+ * and drop that limb; out->level = level - 1, out->scale = scale / q.  CKKS_ELEVEL if
+ * level < 2.  out->data must not overlap a->data. */
+int ckks_rescale(ckks_ctx *ctx, const ckks_ct_batch *a, ckks_ct_batch *out, void *stream);
+
+/* ---- image operations (Sec. 4.4) ---- */
+
+/* k x k mean filter (Sec. 4.4.1) of an H x W image of ciphertexts in row-major order
+ * (img->count == H * W): out(y,x) = rescale(K * sum of in(clamp(y+dy), clamp(x+dx)) over
+ * |dy|, |dx| <= k/2), borders clamped to the edge, with 1/k^2 represented as
+ * K = rint(q_{level-1} / k^2) at scale * q_{level-1}, so out->scale = img->scale.  For k > 1
+ * this is bit-identical to the k^2 - 1 additions, ckks_mul_const(1/k^2) and ckks_rescale.  k in {1, 3, 5, 7}; 2 <= level <= 8
+ * (CKKS_EUNSUPPORTED / CKKS_ELEVEL otherwise).  out has level - 1; out->data must not
+ * overlap img->data. */
+int ckks_mean_filter(ckks_ctx *ctx, const ckks_ct_batch *img, uint32_t H, uint32_t W, uint32_t k,
+                     ckks_ct_batch *out, void *stream);
+
+/* ---- decryption (Sec. 2.2.2) ---- */
+
+/* d_out[t] = slot 0 of decode(c0 + c1*s) for every ciphertext: sum_j x_j cos(pi j/N) / scale,
+ * where x_j is the centered residue of limb 0.  Valid while every |x_j| < q_0/2, which
+ * holds for pixel-sized messages at the supported parameters.  d_out is a device double[count]. */
+int ckks_decrypt_pixels(ckks_ctx *ctx, const ckks_ct_batch *in, double *d_out, void *stream);
+
+/* ---- streams ---- */
+
+/* Wait for all work enqueued on `stream` and report any asynchronous device error. */
+int ckks_stream_sync(ckks_ctx *ctx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKKS_MI355X_H */

@@ -1,0 +1,377 @@
+"""Python binding of libckks_mi355x.so, the MI355X (gfx950) pixel-level CKKS library.
+
+Argument marshalling only: every computation runs in the library's HIP kernels, and
+PyTorch supplies device memory and streams.  The functions carry the names of the C
+ABI in include/ckks_mi355x.h; `Context` bundles them for convenience.  Nothing here
+falls back to the CPU: if the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libckks_mi355x.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ckks_mi355x.h")
+
+CKKS_OK = 0
+ERRORS = {
+    -1: "CKKS_EINVAL", -2: "CKKS_ENOMEM", -3: "CKKS_ENOMEM_BUDGET", -4: "CKKS_EDEVICE", -5: "CKKS_ELEVEL",
+    -6: "CKKS_ESCALE", -7: "CKKS_ECACHE", -8: "CKKS_EUNSUPPORTED", -9: "CKKS_ESTATE",
+}
+CKKS_CACHE_RADIX, CKKS_CACHE_VALUE_TOPK, CKKS_CACHE_VALUE_FULL = 1, 2, 3
+
+
+class CkksError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "CKKS_E?"), code, message))
+        self.code = code
+        self.name = ERRORS.get(code, "CKKS_E?")
+
+
+class ckks_params_t(C.Structure):
+    _fields_ = [("log_n", C.c_uint32), ("num_primes", C.c_uint32), ("prime_bits", C.c_uint32),
+                ("log_scale", C.c_uint32), ("sigma", C.c_double), ("gauss_bound", C.c_uint32),
+                ("reserved", C.c_uint32), ("primes", C.POINTER(C.c_uint64))]
+
+
+class ckks_ct_batch_t(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("count", C.c_uint64), ("level", C.c_uint32), ("reserved", C.c_uint32),
+                ("scale", C.c_double)]
+
+
+class ckks_cache_desc_t(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("base", C.c_uint32), ("digits", C.c_uint32), ("topk", C.c_uint32),
+                ("zero_pool", C.c_uint32)]
+
+
+_lib = None
+
+_SIGS = {
+    "ckks_last_error": (C.c_char_p, []),
+    "ckks_params_resolve": (C.c_int, [C.POINTER(ckks_params_t), C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)]),
+    "ckks_host_cdt_table": (C.c_int, [C.POINTER(ckks_params_t), C.POINTER(C.c_uint64), C.c_uint32]),
+    "ckks_host_encode_table": (C.c_int, [C.POINTER(ckks_params_t), C.POINTER(C.c_double), C.c_uint64]),
+    "ckks_context_create": (C.c_int, [C.POINTER(ckks_params_t), C.c_int, C.POINTER(C.c_void_p)]),
+    "ckks_context_destroy": (None, [C.c_void_p]),
+    "ckks_ct_bytes": (C.c_uint64, [C.c_void_p, C.c_uint32]),
+    "ckks_context_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "ckks_keygen": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "ckks_keys_export": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
+    "ckks_keys_import": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
+    "ckks_encrypt_pixels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_uint64,
+                                      C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_cache_build": (C.c_int, [C.c_void_p, C.POINTER(ckks_cache_desc_t), C.c_void_p, C.c_uint64,
+                                   C.POINTER(C.c_uint64), C.POINTER(C.c_void_p), C.c_void_p]),
+    "ckks_cache_destroy": (None, [C.c_void_p]),
+    "ckks_cache_entries": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32)]),
+    "ckks_cache_export": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                    C.POINTER(C.c_uint64)]),
+    "ckks_encrypt_cached": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64),
+                                      C.c_uint64, C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_add": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.POINTER(ckks_ct_batch_t),
+                           C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_sub": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.POINTER(ckks_ct_batch_t),
+                           C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_mul_const": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_double, C.POINTER(ckks_ct_batch_t),
+                                 C.c_void_p]),
+    "ckks_add_const": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_void_p, C.c_double, C.c_void_p]),
+    "ckks_rescale": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_mean_filter": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_uint32, C.c_uint32, C.c_uint32,
+                                   C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_decrypt_pixels": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_void_p, C.c_void_p]),
+    "ckks_stream_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
+}
+
+
+def lib():
+    """Load the HIP library (after torch, so both share one HIP runtime).  Raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libckks_mi355x.so is not built: run __graft_entry__.build() or "
+                              "python paper_2409_03568_amd/build_native.py")
+        import torch  # noqa: F401  (loads the HIP runtime first)
+
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def ckks_last_error() -> str:
+    return lib().ckks_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != CKKS_OK:
+        raise CkksError(rc, ckks_last_error())
+
+
+def _seed(seed):
+    arr = (C.c_uint64 * 2)(int(seed[0]) & (2**64 - 1), int(seed[1]) & (2**64 - 1))
+    return arr
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# parameters and host-only queries
+# ---------------------------------------------------------------------------
+def ckks_params(log_n: int, num_primes: int, prime_bits: int, log_scale: int, sigma: float = 3.2,
+                gauss_bound: int = 0, primes=None) -> ckks_params_t:
+    p = ckks_params_t(log_n, num_primes, prime_bits, log_scale, sigma, gauss_bound, 0, None)
+    if primes is not None:
+        arr = (C.c_uint64 * len(primes))(*[int(x) for x in primes])
+        p._primes_keep = arr
+        p.primes = C.cast(arr, C.POINTER(C.c_uint64))
+    return p
+
+
+def ckks_params_resolve(params: ckks_params_t):
+    q = (C.c_uint64 * params.num_primes)()
+    B = C.c_uint32(0)
+    _check(lib().ckks_params_resolve(C.byref(params), q, C.byref(B)))
+    return [int(x) for x in q], int(B.value)
+
+
+def ckks_host_cdt_table(params: ckks_params_t) -> np.ndarray:
+    _, B = ckks_params_resolve(params)
+    out = np.zeros(max(1, 2 * B), dtype=np.uint64)
+    _check(lib().ckks_host_cdt_table(C.byref(params), out.ctypes.data_as(C.POINTER(C.c_uint64)), len(out)))
+    return out[: 2 * B]
+
+
+def ckks_host_encode_table(params: ckks_params_t) -> np.ndarray:
+    out = np.zeros(1 << params.log_n, dtype=np.float64)
+    _check(lib().ckks_host_encode_table(C.byref(params), out.ctypes.data_as(C.POINTER(C.c_double)), len(out)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# ciphertext batches in torch device memory
+# ---------------------------------------------------------------------------
+@dataclass
+class Ciphertexts:
+    """count ciphertexts [count][2][level][N] as uint64 residues (stored in an int64 tensor)."""
+
+    data: "object"  # torch.Tensor, int64, on the context's device
+    level: int
+    scale: float
+
+    @property
+    def count(self) -> int:
+        return int(self.data.shape[0])
+
+    def batch(self) -> ckks_ct_batch_t:
+        return ckks_ct_batch_t(self.data.data_ptr() if self.count else None, self.count, self.level, 0, self.scale)
+
+    def to_numpy(self) -> np.ndarray:
+        return self.data.cpu().numpy().view(np.uint64)
+
+    def __getitem__(self, idx) -> "Ciphertexts":
+        d = self.data[idx]
+        if d.dim() == 3:
+            d = d.unsqueeze(0)
+        return Ciphertexts(d, self.level, self.scale)
+
+
+class Context:
+    """A parameter set on one GPU with its keys (wraps ckks_context_create)."""
+
+    def __init__(self, log_n: int, num_primes: int, prime_bits: int, log_scale: int, sigma: float = 3.2,
+                 gauss_bound: int = 0, primes=None, device: int = 0):
+        import torch
+
+        self.params = ckks_params(log_n, num_primes, prime_bits, log_scale, sigma, gauss_bound, primes)
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        _check(lib().ckks_context_create(C.byref(self.params), device, C.byref(h)))
+        self.handle = h
+        self.N = 1 << log_n
+        self.L = num_primes
+        self.scale = float(2.0**log_scale)
+        q = (C.c_uint64 * num_primes)()
+        _check(lib().ckks_context_info(self.handle, None, None, None, q))
+        self.q = [int(x) for x in q]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ckks_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- memory -------------------------------------------------------------
+    def ct_bytes(self, level: int | None = None) -> int:
+        return int(lib().ckks_ct_bytes(self.handle, self.L if level is None else level))
+
+    def empty(self, n: int, level: int | None = None) -> Ciphertexts:
+        import torch
+
+        level = self.L if level is None else level
+        return Ciphertexts(torch.empty((n, 2, level, self.N), dtype=torch.int64, device=self.device), level,
+                           self.scale)
+
+    def from_numpy(self, arr, level: int | None = None, scale: float | None = None) -> Ciphertexts:
+        import torch
+
+        level = self.L if level is None else level
+        a = np.ascontiguousarray(arr, dtype=np.uint64).reshape(-1, 2, level, self.N).view(np.int64)
+        return Ciphertexts(torch.from_numpy(a.copy()).to(self.device), level, self.scale if scale is None else scale)
+
+    # -- keys ---------------------------------------------------------------
+    def keygen(self, seed):
+        _check(lib().ckks_keygen(self.handle, _seed(seed)))
+
+    def keys_export(self):
+        s = np.zeros(self.N, dtype=np.int64)
+        pk = np.zeros(2 * self.L * self.N, dtype=np.uint64)
+        _check(lib().ckks_keys_export(self.handle, s.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      pk.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return s, pk
+
+    def keys_import(self, s, pk):
+        s = np.ascontiguousarray(s, dtype=np.int64)
+        pk = np.ascontiguousarray(pk, dtype=np.uint64).reshape(-1)
+        _check(lib().ckks_keys_import(self.handle, s.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      pk.ctypes.data_as(C.POINTER(C.c_uint64))))
+
+    # -- encryption -------------------------------------------------------------
+    def encrypt_pixels(self, px, seed, first_index: int = 0, out: Ciphertexts | None = None,
+                       stream=None) -> Ciphertexts:
+        n = int(px.numel())
+        out = self.empty(n) if out is None else out
+        b = out.batch()
+        _check(lib().ckks_encrypt_pixels(self.handle, _ptr(px), n, _seed(seed), first_index, C.byref(b),
+                                         _stream(stream)))
+        out.level, out.scale = int(b.level), float(b.scale)
+        return out
+
+    def cache_build(self, kind: int, base: int = 0, digits: int = 0, topk: int = 0, zero_pool: int = 0,
+                    scan_px=None, seed=(0, 0), stream=None) -> "Cache":
+        desc = ckks_cache_desc_t(kind, base, digits, topk, zero_pool)
+        h = C.c_void_p()
+        n_scan = 0 if scan_px is None else int(scan_px.numel())
+        _check(lib().ckks_cache_build(self.handle, C.byref(desc), _ptr(scan_px), n_scan, _seed(seed), C.byref(h),
+                                      _stream(stream)))
+        return Cache(h, self, kind)
+
+    def encrypt_cached(self, cache: "Cache", px, seed, first_index: int = 0, out: Ciphertexts | None = None,
+                       stream=None) -> Ciphertexts:
+        n = int(px.numel())
+        out = self.empty(n) if out is None else out
+        b = out.batch()
+        _check(lib().ckks_encrypt_cached(self.handle, cache.handle, _ptr(px), n, _seed(seed), first_index,
+                                         C.byref(b), _stream(stream)))
+        out.level, out.scale = int(b.level), float(b.scale)
+        return out
+
+    # -- homomorphic operations ---------------------------------------------------
+    def _binary(self, fn, a: Ciphertexts, b: Ciphertexts, out, stream):
+        out = self.empty(a.count, a.level) if out is None else out
+        ba, bb, bo = a.batch(), b.batch(), out.batch()
+        _check(fn(self.handle, C.byref(ba), C.byref(bb), C.byref(bo), _stream(stream)))
+        out.level, out.scale = int(bo.level), float(bo.scale)
+        return out
+
+    def add(self, a, b, out=None, stream=None) -> Ciphertexts:
+        return self._binary(lib().ckks_add, a, b, out, stream)
+
+    def sub(self, a, b, out=None, stream=None) -> Ciphertexts:
+        return self._binary(lib().ckks_sub, a, b, out, stream)
+
+    def mul_const(self, a: Ciphertexts, c: float, out=None, stream=None) -> Ciphertexts:
+        out = self.empty(a.count, a.level) if out is None else out
+        ba, bo = a.batch(), out.batch()
+        _check(lib().ckks_mul_const(self.handle, C.byref(ba), float(c), C.byref(bo), _stream(stream)))
+        out.level, out.scale = int(bo.level), float(bo.scale)
+        return out
+
+    def add_const(self, a: Ciphertexts, b=0.0, per_ct=None, stream=None) -> Ciphertexts:
+        ba = a.batch()
+        _check(lib().ckks_add_const(self.handle, C.byref(ba), _ptr(per_ct), float(b), _stream(stream)))
+        return a
+
+    def rescale(self, a: Ciphertexts, out=None, stream=None) -> Ciphertexts:
+        out = self.empty(a.count, a.level - 1) if out is None else out
+        ba, bo = a.batch(), out.batch()
+        _check(lib().ckks_rescale(self.handle, C.byref(ba), C.byref(bo), _stream(stream)))
+        out.level, out.scale = int(bo.level), float(bo.scale)
+        return out
+
+    def mean_filter(self, img: Ciphertexts, H: int, W: int, k: int, out=None, stream=None) -> Ciphertexts:
+        out = self.empty(img.count, img.level - 1) if out is None else out
+        bi, bo = img.batch(), out.batch()
+        _check(lib().ckks_mean_filter(self.handle, C.byref(bi), H, W, k, C.byref(bo), _stream(stream)))
+        out.level, out.scale = int(bo.level), float(bo.scale)
+        return out
+
+    def decrypt_pixels(self, cts: Ciphertexts, out=None, stream=None):
+        import torch
+
+        out = torch.empty(cts.count, dtype=torch.float64, device=self.device) if out is None else out
+        b = cts.batch()
+        _check(lib().ckks_decrypt_pixels(self.handle, C.byref(b), _ptr(out), _stream(stream)))
+        return out
+
+    def stream_sync(self, stream=None):
+        _check(lib().ckks_stream_sync(self.handle, _stream(stream)))
+
+
+class Cache:
+    def __init__(self, handle, ctx: Context, kind: int):
+        self.handle = handle
+        self.ctx = ctx
+        self.kind = kind
+
+    def entries(self) -> int:
+        n = C.c_uint32(0)
+        _check(lib().ckks_cache_entries(self.handle, C.byref(n)))
+        return int(n.value)
+
+    def export(self, pool_size: int = 0):
+        """(values[n], entries[n][2][L][N], pool[pool_size][2][L][N]) as numpy arrays."""
+        n = self.entries()
+        S = 2 * self.ctx.L * self.ctx.N
+        vals = np.zeros(max(n, 1), dtype=np.uint32)
+        ent = np.zeros(max(n, 1) * S, dtype=np.uint64)
+        pool = np.zeros(max(pool_size, 1) * S, dtype=np.uint64)
+        _check(lib().ckks_cache_export(self.handle, vals.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                       ent.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                       pool.ctypes.data_as(C.POINTER(C.c_uint64)) if pool_size else None))
+        return vals[:n], ent[: n * S].reshape(n, S), pool[: pool_size * S].reshape(pool_size, S)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ckks_cache_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,668 @@
+// C ABI: argument validation, context and cache management, and kernel dispatch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "modarith.hpp"
+#include "philox.hpp"
+
+using namespace ckks;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(CKKS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                         \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Keeps the caller's current device and restores it on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+template <typename T>
+hipError_t upload(T *dst, const std::vector<T> &src) {
+  return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+int resolve_params(const ckks_params *p, host::Resolved *r) {
+  if (!p) return fail(CKKS_EINVAL, "params is NULL");
+  int code = CKKS_OK;
+  std::string why = host::resolve(p->log_n, p->num_primes, p->prime_bits, p->log_scale, p->sigma, p->gauss_bound,
+                                  p->primes, r, &code);
+  if (code != CKKS_OK) return fail(code, "%s", why.c_str());
+  return CKKS_OK;
+}
+
+void free_tables(ckks_ctx *c) {
+  DevTables &d = c->dev;
+  void *ptrs[] = {d.tw_fwd, d.tw_inv, d.enc_T, d.cosj, d.cdt, d.s, d.pk, d.pk_hat, d.s_hat};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  d = DevTables{};
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+uint64_t ct_words(const ckks_ctx *c, uint32_t level) { return (uint64_t)2 * level * (uint64_t)c->N; }
+
+int check_ctx(const ckks_ctx *c) {
+  if (!c) return fail(CKKS_EINVAL, "context is NULL");
+  return CKKS_OK;
+}
+
+int check_keys(const ckks_ctx *c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->has_keys) return fail(CKKS_ESTATE, "no keys: call ckks_keygen or ckks_keys_import first");
+  return CKKS_OK;
+}
+
+int check_batch(const ckks_ctx *c, const ckks_ct_batch *b, const char *name) {
+  if (!b) return fail(CKKS_EINVAL, "%s is NULL", name);
+  if (b->level < 1 || b->level > (uint32_t)c->prm.L) return fail(CKKS_ELEVEL, "%s: level %u outside [1, %d]", name, b->level, c->prm.L);
+  if (b->count && !b->data) return fail(CKKS_EINVAL, "%s: data is NULL", name);
+  if (!(b->scale > 0.0) || !isfinite(b->scale)) return fail(CKKS_ESCALE, "%s: scale must be positive and finite", name);
+  return CKKS_OK;
+}
+
+// Constant c as a per-limb multiplier (integer c keeps the scale unless `scaled`; any
+// other c becomes K = rint(c * q_{level-1}) at scale * q_{level-1}).
+int const_multiplier(const ckks_ctx *c, uint32_t level, double scale, double cst, std::vector<uint64_t> &K,
+                     double *new_scale, bool scaled = false) {
+  if (!isfinite(cst)) return fail(CKKS_EINVAL, "constant is not finite");
+  double Kd = cst;
+  double ns = scale;
+  if (scaled || cst != rint(cst)) {
+    const double ql = (double)c->prm.q[level - 1];
+    Kd = rint(cst * ql);
+    ns = scale * ql;
+  }
+  if (!isfinite(Kd) || !isfinite(ns)) return fail(CKKS_ESCALE, "scaled constant overflows");
+  K.resize(level);
+  for (uint32_t i = 0; i < level; i++) {
+    const uint64_t q = c->prm.q[i];
+    K[i] = residue_of_double(Kd, q, 1.0 / (double)q);
+  }
+  *new_scale = ns;
+  return CKKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ckks_last_error(void) { return g_err.c_str(); }
+
+int ckks_params_resolve(const ckks_params *params, uint64_t *host_primes, uint32_t *gauss_bound) {
+  host::Resolved r;
+  int rc = resolve_params(params, &r);
+  if (rc) return rc;
+  if (host_primes)
+    for (int i = 0; i < r.L; i++) host_primes[i] = r.q[(size_t)i];
+  if (gauss_bound) *gauss_bound = (uint32_t)r.B;
+  return CKKS_OK;
+}
+
+int ckks_host_cdt_table(const ckks_params *params, uint64_t *host_out, uint32_t capacity) {
+  host::Resolved r;
+  int rc = resolve_params(params, &r);
+  if (rc) return rc;
+  if ((uint32_t)(2 * r.B) > capacity || (!host_out && r.B)) return fail(CKKS_EINVAL, "need room for %d entries", 2 * r.B);
+  std::vector<uint64_t> T = host::cdt_table(r.sigma, r.B, kCdtSlots);
+  for (int k = 0; k < 2 * r.B; k++) host_out[k] = T[(size_t)k];
+  return CKKS_OK;
+}
+
+int ckks_host_encode_table(const ckks_params *params, double *host_out, uint64_t capacity) {
+  host::Resolved r;
+  int rc = resolve_params(params, &r);
+  if (rc) return rc;
+  const uint64_t N = 1ULL << r.log_n;
+  if (!host_out || capacity < N) return fail(CKKS_EINVAL, "need room for %llu entries", (unsigned long long)N);
+  std::vector<double> T = host::encode_table(r.log_n, r.log_scale);
+  memcpy(host_out, T.data(), N * sizeof(double));
+  return CKKS_OK;
+}
+
+int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
+  if (!out) return fail(CKKS_EINVAL, "out is NULL");
+  *out = nullptr;
+  host::Resolved r;
+  int rc = resolve_params(params, &r);
+  if (rc) return rc;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(CKKS_EINVAL, "device %d outside [0, %d)", device, ndev);
+  DeviceGuard g(device);
+  ckks_ctx *c = new ckks_ctx();
+  c->device = device;
+  c->prm = r;
+  c->N = 1 << r.log_n;
+  c->scale = ldexp(1.0, r.log_scale);
+  const int N = c->N, L = r.L;
+  LimbConsts &lc = c->lc;
+  memset(&lc, 0, sizeof(lc));
+  lc.L = L;
+  lc.B = r.B;
+  double qmax = 0;
+  std::vector<double> twf((size_t)L * N), twi((size_t)L * N);
+  for (int i = 0; i < L; i++) {
+    const uint64_t q = r.q[(size_t)i];
+    lc.q[i] = (double)q;
+    lc.qinv[i] = 1.0 / (double)q;
+    lc.qi[i] = q;
+    const uint64_t ni = host::inv_mod((uint64_t)N % q, q);
+    c->ninv.push_back(ni);
+    lc.ninv[i] = host::centered(ni, q);
+    qmax = std::max(qmax, (double)q);
+    std::vector<double> f, iv;
+    host::twiddles(q, r.psi[(size_t)i], r.log_n, f, iv);
+    std::copy(f.begin(), f.end(), twf.begin() + (size_t)i * N);
+    std::copy(iv.begin(), iv.end(), twi.begin() + (size_t)i * N);
+  }
+  // forward transforms start from ternary/Gaussian values (|x| <= 1) or canonical
+  // residues (< q); inverse transforms start from pointwise products of a value below
+  // 2^51 with a reduced key value (<= 3q/4 + 2)
+  lc.red_fwd = host::forward_reduction_mask(r.log_n, qmax, 1.0);
+  lc.red_fwd_big = host::forward_reduction_mask(r.log_n, qmax, qmax);
+  lc.red_inv = host::inverse_reduction_mask(r.log_n, qmax, 0.75 * qmax + 4);
+  hipError_t e = hipSuccess;
+  DevTables &d = c->dev;
+  if (e == hipSuccess) e = dev_alloc(&d.tw_fwd, (size_t)L * N);
+  if (e == hipSuccess) e = dev_alloc(&d.tw_inv, (size_t)L * N);
+  if (e == hipSuccess) e = dev_alloc(&d.enc_T, (size_t)N);
+  if (e == hipSuccess) e = dev_alloc(&d.cosj, (size_t)N);
+  if (e == hipSuccess) e = dev_alloc(&d.cdt, (size_t)kCdtSlots);
+  if (e == hipSuccess) e = dev_alloc(&d.s, (size_t)N);
+  if (e == hipSuccess) e = dev_alloc(&d.pk, (size_t)2 * L * N);
+  if (e == hipSuccess) e = dev_alloc(&d.pk_hat, (size_t)2 * L * N);
+  if (e == hipSuccess) e = dev_alloc(&d.s_hat, (size_t)L * N);
+  if (e != hipSuccess) {
+    free_tables(c);
+    delete c;
+    return fail(CKKS_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  if (e == hipSuccess) e = upload(d.tw_fwd, twf);
+  if (e == hipSuccess) e = upload(d.tw_inv, twi);
+  if (e == hipSuccess) e = upload(d.enc_T, host::encode_table(r.log_n, r.log_scale));
+  if (e == hipSuccess) e = upload(d.cosj, host::cos_table(r.log_n));
+  if (e == hipSuccess) e = upload(d.cdt, host::cdt_table(r.sigma, r.B, kCdtSlots));
+  if (e != hipSuccess) {
+    free_tables(c);
+    delete c;
+    return hip_fail(e, "uploading tables");
+  }
+  *out = c;
+  return CKKS_OK;
+}
+
+void ckks_context_destroy(ckks_ctx *ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_tables(ctx);
+  delete ctx;
+}
+
+uint64_t ckks_ct_bytes(const ckks_ctx *ctx, uint32_t level) {
+  if (!ctx || level < 1 || level > (uint32_t)ctx->prm.L) return 0;
+  return ct_words(ctx, level) * sizeof(uint64_t);
+}
+
+int ckks_context_info(const ckks_ctx *ctx, uint32_t *log_n, uint32_t *num_primes, double *scale,
+                      uint64_t *host_primes) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (log_n) *log_n = (uint32_t)ctx->prm.log_n;
+  if (num_primes) *num_primes = (uint32_t)ctx->prm.L;
+  if (scale) *scale = ctx->scale;
+  if (host_primes)
+    for (int i = 0; i < ctx->prm.L; i++) host_primes[i] = ctx->prm.q[(size_t)i];
+  return CKKS_OK;
+}
+
+int ckks_keygen(ckks_ctx *ctx, const uint64_t seed[2]) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!seed) return fail(CKKS_EINVAL, "seed is NULL");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_keygen(ctx, seed[0], seed[1], nullptr), "keygen launch");
+  HIP_TRY(launch_keys_prepare(ctx, nullptr), "key preparation launch");
+  HIP_TRY(hipDeviceSynchronize(), "keygen");
+  ctx->has_keys = true;
+  return CKKS_OK;
+}
+
+int ckks_keys_export(ckks_ctx *ctx, int64_t *host_s, uint64_t *host_pk) {
+  int rc = check_keys(ctx);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  const size_t N = (size_t)ctx->N, L = (size_t)ctx->prm.L;
+  if (host_s) HIP_TRY(hipMemcpy(host_s, ctx->dev.s, N * sizeof(int64_t), hipMemcpyDeviceToHost), "export s");
+  if (host_pk) HIP_TRY(hipMemcpy(host_pk, ctx->dev.pk, 2 * L * N * sizeof(uint64_t), hipMemcpyDeviceToHost), "export pk");
+  return CKKS_OK;
+}
+
+int ckks_keys_import(ckks_ctx *ctx, const int64_t *host_s, const uint64_t *host_pk) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!host_s || !host_pk) return fail(CKKS_EINVAL, "keys are NULL");
+  const size_t N = (size_t)ctx->N, L = (size_t)ctx->prm.L;
+  for (size_t j = 0; j < N; j++)
+    if (host_s[j] < -1 || host_s[j] > 1) return fail(CKKS_EINVAL, "secret key coefficient %zu not in {-1,0,1}", j);
+  for (size_t p = 0; p < 2; p++)
+    for (size_t i = 0; i < L; i++)
+      for (size_t j = 0; j < N; j++)
+        if (host_pk[(p * L + i) * N + j] >= ctx->prm.q[i]) return fail(CKKS_EINVAL, "public key residue not canonical");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(hipMemcpy(ctx->dev.s, host_s, N * sizeof(int64_t), hipMemcpyHostToDevice), "import s");
+  HIP_TRY(hipMemcpy(ctx->dev.pk, host_pk, 2 * L * N * sizeof(uint64_t), hipMemcpyHostToDevice), "import pk");
+  HIP_TRY(launch_keys_prepare(ctx, nullptr), "key preparation launch");
+  HIP_TRY(hipDeviceSynchronize(), "key preparation");
+  ctx->has_keys = true;
+  return CKKS_OK;
+}
+
+int ckks_encrypt_pixels(ckks_ctx *ctx, const uint8_t *d_px, uint64_t n, const uint64_t seed[2],
+                        uint64_t first_index, ckks_ct_batch *out, void *stream) {
+  int rc = check_keys(ctx);
+  if (rc) return rc;
+  if (!seed || !out) return fail(CKKS_EINVAL, "seed/out is NULL");
+  if (n && (!d_px || !out->data)) return fail(CKKS_EINVAL, "pixel or output pointer is NULL");
+  if (n > 0xFFFFFFFFull) return fail(CKKS_EINVAL, "at most 2^32-1 pixels per call");
+  out->count = n;
+  out->level = (uint32_t)ctx->prm.L;
+  out->scale = ctx->scale;
+  if (n == 0) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  EncJob job;
+  job.px = d_px;
+  job.n = n;
+  job.first_index = first_index;
+  job.seed0 = seed[0];
+  job.seed1 = seed[1];
+  job.out = out->data;
+  const uint64_t grid = std::min<uint64_t>(n, 1u << 24);
+  HIP_TRY(launch_encrypt(ctx, job, grid, as_stream(stream)), "encrypt launch");
+  return CKKS_OK;
+}
+
+int ckks_cache_build(ckks_ctx *ctx, const ckks_cache_desc *desc, const uint8_t *d_scan, uint64_t n_scan,
+                     const uint64_t cache_seed[2], ckks_cache **out, void *stream) {
+  int rc = check_keys(ctx);
+  if (rc) return rc;
+  if (!desc || !cache_seed || !out) return fail(CKKS_EINVAL, "desc/seed/out is NULL");
+  *out = nullptr;
+  const int kind = desc->kind;
+  uint32_t n_slots = 0;
+  std::vector<uint32_t> vals;
+  std::vector<uint64_t> ts;
+  std::vector<int16_t> slot_of(256, -1);
+  if (kind == CKKS_CACHE_RADIX) {
+    const uint32_t r = desc->base, D = desc->digits;
+    if (r < 2 || r > 256 || D < 1 || D > (uint32_t)kMaxDigits) return fail(CKKS_ECACHE, "radix base must be in [2,256], digits in [1,8]");
+    uint64_t pw = 1;
+    for (uint32_t i = 0; i + 1 < D; i++) pw *= r;
+    if (pw > 255) return fail(CKKS_ECACHE, "base^(digits-1) = %llu exceeds 255", (unsigned long long)pw);
+    if (pw * r < 256) return fail(CKKS_ECACHE, "base^digits must be >= 256 to cover every pixel");
+    n_slots = D + 1;
+    vals.push_back(0);
+    ts.push_back(0);
+    pw = 1;
+    for (uint32_t i = 0; i < D; i++) {
+      vals.push_back((uint32_t)pw);
+      ts.push_back(1 + i);
+      pw *= r;
+    }
+  } else if (kind == CKKS_CACHE_VALUE_TOPK || kind == CKKS_CACHE_VALUE_FULL) {
+    if (desc->zero_pool < 1 || desc->zero_pool > 4096) return fail(CKKS_ECACHE, "zero_pool must be in [1, 4096]");
+    if (kind == CKKS_CACHE_VALUE_TOPK) {
+      if (desc->topk < 1 || desc->topk > 256) return fail(CKKS_ECACHE, "topk must be in [1, 256]");
+      if (n_scan && !d_scan) return fail(CKKS_EINVAL, "scan pixels are NULL");
+      if (n_scan > 0xFFFFFFFFull) return fail(CKKS_EINVAL, "at most 2^32-1 scan pixels");
+      n_slots = desc->topk;
+      vals.assign(n_slots, 0);
+      ts.assign(n_slots, 0);
+    } else {
+      n_slots = 256;
+      for (uint32_t v = 0; v < 256; v++) {
+        vals.push_back(v);
+        ts.push_back(256 + v);
+        slot_of[v] = (int16_t)v;
+      }
+    }
+  } else {
+    return fail(CKKS_ECACHE, "unknown cache kind %d", kind);
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  ckks_cache *c = new ckks_cache();
+  c->ctx = ctx;
+  c->device = ctx->device;
+  c->kind = kind;
+  c->base = desc->base;
+  c->digits = desc->digits;
+  c->topk = desc->topk;
+  c->pool = (kind == CKKS_CACHE_RADIX) ? 0 : desc->zero_pool;
+  c->n_slots = n_slots;
+  const uint64_t S = ct_words(ctx, (uint32_t)ctx->prm.L);
+  hipError_t e = dev_alloc(&c->entries, (size_t)n_slots * S);
+  if (e == hipSuccess && c->pool) e = dev_alloc(&c->pool_cts, (size_t)c->pool * S);
+  if (e == hipSuccess) e = dev_alloc(&c->slot_of, 256);
+  if (e == hipSuccess) e = dev_alloc(&c->vals, n_slots);
+  if (e == hipSuccess) e = dev_alloc(&c->ts, n_slots);
+  if (e == hipSuccess) e = dev_alloc(&c->count, 1);
+  if (e != hipSuccess) {
+    ckks_cache_destroy(c);
+    return fail(CKKS_ENOMEM, "cache allocation failed: %s", hipGetErrorString(e));
+  }
+  // setup arrays are copied synchronously, before any work is enqueued on the stream
+  const uint32_t count = n_slots;
+  e = upload(c->slot_of, slot_of);
+  if (e == hipSuccess) e = upload(c->vals, vals);
+  if (e == hipSuccess) e = upload(c->ts, ts);
+  if (e == hipSuccess) e = hipMemcpy(c->count, &count, sizeof(count), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    ckks_cache_destroy(c);
+    return hip_fail(e, "cache setup copy");
+  }
+  uint32_t *hist = nullptr;
+  if (kind == CKKS_CACHE_VALUE_TOPK) {
+    e = hipMallocAsync(reinterpret_cast<void **>(&hist), 256 * sizeof(uint32_t), st);
+    if (e == hipSuccess) e = launch_histogram_topk(ctx, d_scan, n_scan, desc->topk, hist, c, st);
+    if (e == hipSuccess) e = hipFreeAsync(hist, st);
+  }
+  if (e == hipSuccess) {
+    EncJob job;
+    job.vals = c->vals;
+    job.ts = c->ts;
+    job.list_count = c->count;
+    job.n = n_slots;
+    job.seed0 = cache_seed[0];
+    job.seed1 = cache_seed[1];
+    job.out = c->entries;
+    e = launch_encrypt(ctx, job, n_slots, st);
+  }
+  if (e == hipSuccess && c->pool) {
+    // pool member u = Enc(0) at Philox index 512 + u
+    std::vector<uint32_t> zv(c->pool, 0);
+    std::vector<uint64_t> zt(c->pool);
+    for (uint32_t u = 0; u < c->pool; u++) zt[u] = 512 + (uint64_t)u;
+    uint32_t *d_zv = nullptr;
+    uint64_t *d_zt = nullptr;
+    e = dev_alloc(&d_zv, c->pool);
+    if (e == hipSuccess) e = dev_alloc(&d_zt, c->pool);
+    if (e == hipSuccess) e = upload(d_zv, zv);
+    if (e == hipSuccess) e = upload(d_zt, zt);
+    if (e == hipSuccess) {
+      EncJob job;
+      job.vals = d_zv;
+      job.ts = d_zt;
+      job.n = c->pool;
+      job.seed0 = cache_seed[0];
+      job.seed1 = cache_seed[1];
+      job.out = c->pool_cts;
+      e = launch_encrypt(ctx, job, c->pool, st);
+    }
+    // the temporary arrays are released once the stream has consumed them
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (d_zv) (void)hipFree(d_zv);
+    if (d_zt) (void)hipFree(d_zt);
+  }
+  if (e != hipSuccess) {
+    ckks_cache_destroy(c);
+    return hip_fail(e, "cache build");
+  }
+  *out = c;
+  return CKKS_OK;
+}
+
+void ckks_cache_destroy(ckks_cache *c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  void *ptrs[] = {c->entries, c->pool_cts, c->slot_of, c->vals, c->ts, c->count};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+int ckks_cache_entries(ckks_cache *cache, uint32_t *n_entries) {
+  if (!cache || !n_entries) return fail(CKKS_EINVAL, "cache/n_entries is NULL");
+  DeviceGuard g(cache->device);
+  HIP_TRY(hipDeviceSynchronize(), "cache build");
+  HIP_TRY(hipMemcpy(n_entries, cache->count, sizeof(uint32_t), hipMemcpyDeviceToHost), "cache count");
+  return CKKS_OK;
+}
+
+int ckks_cache_export(ckks_cache *cache, uint32_t *host_values, uint64_t *host_entries, uint64_t *host_pool) {
+  uint32_t n = 0;
+  int rc = ckks_cache_entries(cache, &n);
+  if (rc) return rc;
+  DeviceGuard g(cache->device);
+  const size_t S = (size_t)ct_words(cache->ctx, (uint32_t)cache->ctx->prm.L);
+  if (host_values) HIP_TRY(hipMemcpy(host_values, cache->vals, n * sizeof(uint32_t), hipMemcpyDeviceToHost), "cache values");
+  if (host_entries)
+    HIP_TRY(hipMemcpy(host_entries, cache->entries, (size_t)n * S * sizeof(uint64_t), hipMemcpyDeviceToHost), "cache entries");
+  if (host_pool && cache->pool)
+    HIP_TRY(hipMemcpy(host_pool, cache->pool_cts, (size_t)cache->pool * S * sizeof(uint64_t), hipMemcpyDeviceToHost),
+            "cache pool");
+  return CKKS_OK;
+}
+
+int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
+                        const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream) {
+  int rc = check_keys(ctx);
+  if (rc) return rc;
+  if (!cache || cache->ctx != ctx) return fail(CKKS_ECACHE, "cache is NULL or belongs to another context");
+  if (!seed || !out) return fail(CKKS_EINVAL, "seed/out is NULL");
+  if (n && (!d_px || !out->data)) return fail(CKKS_EINVAL, "pixel or output pointer is NULL");
+  if (n > 0xFFFFFFFFull) return fail(CKKS_EINVAL, "at most 2^32-1 pixels per call");
+  out->count = n;
+  out->level = (uint32_t)ctx->prm.L;
+  out->scale = ctx->scale;
+  if (n == 0) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  if (cache->kind == CKKS_CACHE_RADIX) {
+    int16_t *meta = nullptr;
+    uint32_t *bad = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&meta), n * kMaxDigits * sizeof(int16_t), st), "meta alloc");
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&bad), sizeof(uint32_t), st), "flag alloc");
+    HIP_TRY(launch_radix_meta(ctx, cache, d_px, n, first_index, seed[0], seed[1], meta, bad, st), "radix meta");
+    HIP_TRY(launch_radix_gather(ctx, cache, meta, n, out->data, st), "radix gather");
+    HIP_TRY(hipFreeAsync(meta, st), "meta free");
+    HIP_TRY(hipFreeAsync(bad, st), "flag free");
+    return CKKS_OK;
+  }
+  uint32_t *meta = nullptr, *miss = nullptr, *nmiss = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&meta), n * sizeof(uint32_t), st), "meta alloc");
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&miss), n * sizeof(uint32_t), st), "miss list alloc");
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&nmiss), sizeof(uint32_t), st), "miss count alloc");
+  HIP_TRY(launch_value_meta(ctx, cache, d_px, n, first_index, seed[0], seed[1], meta, miss, nmiss, st), "value meta");
+  HIP_TRY(launch_value_gather(ctx, cache, meta, n, out->data, st), "value gather");
+  EncJob job;
+  job.px = d_px;
+  job.list = miss;
+  job.list_count = nmiss;
+  job.n = n;
+  job.first_index = first_index;
+  job.seed0 = seed[0];
+  job.seed1 = seed[1];
+  job.out = out->data;
+  HIP_TRY(launch_encrypt(ctx, job, std::min<uint64_t>(n, kListGrid), st), "miss encryption");
+  HIP_TRY(hipFreeAsync(meta, st), "meta free");
+  HIP_TRY(hipFreeAsync(miss, st), "miss list free");
+  HIP_TRY(hipFreeAsync(nmiss, st), "miss count free");
+  return CKKS_OK;
+}
+
+static int binary_common(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if ((rc = check_batch(ctx, a, "a")) || (rc = check_batch(ctx, b, "b"))) return rc;
+  if (!out) return fail(CKKS_EINVAL, "out is NULL");
+  if (a->count != b->count) return fail(CKKS_EINVAL, "counts differ (%llu vs %llu)", (unsigned long long)a->count, (unsigned long long)b->count);
+  if (a->level != b->level) return fail(CKKS_ELEVEL, "levels differ (%u vs %u)", a->level, b->level);
+  if (a->scale != b->scale) return fail(CKKS_ESCALE, "scales differ (%.17g vs %.17g)", a->scale, b->scale);
+  if (a->count && !out->data) return fail(CKKS_EINVAL, "out data is NULL");
+  return CKKS_OK;
+}
+
+int ckks_add(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream) {
+  int rc = binary_common(ctx, a, b, out);
+  if (rc) return rc;
+  const ckks_ct_batch av = *a;
+  out->count = av.count;
+  out->level = av.level;
+  out->scale = av.scale;
+  if (!av.count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_add_sub(ctx, av.data, b->data, out->data, av.count, (int)av.level, false, as_stream(stream)), "add");
+  return CKKS_OK;
+}
+
+int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream) {
+  int rc = binary_common(ctx, a, b, out);
+  if (rc) return rc;
+  const ckks_ct_batch av = *a;
+  out->count = av.count;
+  out->level = av.level;
+  out->scale = av.scale;
+  if (!av.count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_add_sub(ctx, av.data, b->data, out->data, av.count, (int)av.level, true, as_stream(stream)), "sub");
+  return CKKS_OK;
+}
+
+int ckks_mul_const(ckks_ctx *ctx, const ckks_ct_batch *a, double c, ckks_ct_batch *out, void *stream) {
+  int rc = check_ctx(ctx);
+  if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
+  if (!out || (a->count && !out->data)) return fail(CKKS_EINVAL, "out is NULL");
+  std::vector<uint64_t> K;
+  double ns = 0;
+  if ((rc = const_multiplier(ctx, a->level, a->scale, c, K, &ns))) return rc;
+  const ckks_ct_batch av = *a;
+  out->count = av.count;
+  out->level = av.level;
+  out->scale = ns;
+  if (!av.count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_mul_const(ctx, av.data, out->data, av.count, (int)av.level, K.data(), as_stream(stream)), "mul_const");
+  return CKKS_OK;
+}
+
+int ckks_add_const(ckks_ctx *ctx, ckks_ct_batch *a, const double *d_b, double b, void *stream) {
+  int rc = check_ctx(ctx);
+  if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
+  if (!d_b && !isfinite(b)) return fail(CKKS_EINVAL, "b is not finite");
+  if (!a->count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_add_const(ctx, a->data, a->count, (int)a->level, a->scale, d_b, b, as_stream(stream)), "add_const");
+  return CKKS_OK;
+}
+
+static bool overlaps(const uint64_t *a, uint64_t an, const uint64_t *b, uint64_t bn) {
+  return a < b + bn && b < a + an;
+}
+
+int ckks_rescale(ckks_ctx *ctx, const ckks_ct_batch *a, ckks_ct_batch *out, void *stream) {
+  int rc = check_ctx(ctx);
+  if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
+  if (a->level < 2) return fail(CKKS_ELEVEL, "rescale needs level >= 2");
+  if (!out || (a->count && !out->data)) return fail(CKKS_EINVAL, "out is NULL");
+  const uint64_t nin = a->count * ct_words(ctx, a->level), nout = a->count * ct_words(ctx, a->level - 1);
+  if (a->count && overlaps(a->data, nin, out->data, nout)) return fail(CKKS_EINVAL, "rescale output overlaps its input");
+  const ckks_ct_batch av = *a;
+  out->count = av.count;
+  out->level = av.level - 1;
+  out->scale = av.scale / (double)ctx->prm.q[av.level - 1];
+  if (!av.count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_rescale(ctx, av.data, out->data, av.count, (int)av.level, as_stream(stream)), "rescale");
+  return CKKS_OK;
+}
+
+int ckks_mean_filter(ckks_ctx *ctx, const ckks_ct_batch *img, uint32_t H, uint32_t W, uint32_t k, ckks_ct_batch *out,
+                     void *stream) {
+  int rc = check_ctx(ctx);
+  if (rc || (rc = check_batch(ctx, img, "img"))) return rc;
+  if (k != 1 && k != 3 && k != 5 && k != 7) return fail(CKKS_EUNSUPPORTED, "window k must be 1, 3, 5 or 7");
+  if (img->level < 2 || img->level > 8) return fail(CKKS_ELEVEL, "mean filter needs 2 <= level <= 8");
+  if ((uint64_t)H * W != img->count) return fail(CKKS_EINVAL, "H*W (%llu) != count (%llu)", (unsigned long long)H * W, (unsigned long long)img->count);
+  if (!out || (img->count && !out->data)) return fail(CKKS_EINVAL, "out is NULL");
+  const uint64_t nin = img->count * ct_words(ctx, img->level), nout = img->count * ct_words(ctx, img->level - 1);
+  if (img->count && overlaps(img->data, nin, out->data, nout)) return fail(CKKS_EINVAL, "filter output overlaps its input");
+  std::vector<uint64_t> K;
+  double s1 = 0;
+  // 1/k^2 always in the scaled form rint(q_{level-1} / k^2), so the rescale restores the scale
+  if ((rc = const_multiplier(ctx, img->level, img->scale, 1.0 / (double)(k * k), K, &s1, true))) return rc;
+  const ckks_ct_batch iv = *img;
+  out->count = iv.count;
+  out->level = iv.level - 1;
+  out->scale = s1 / (double)ctx->prm.q[iv.level - 1];
+  if (!iv.count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_mean_filter(ctx, iv.data, out->data, H, W, k, (int)iv.level, K.data(), as_stream(stream)), "mean filter");
+  return CKKS_OK;
+}
+
+int ckks_decrypt_pixels(ckks_ctx *ctx, const ckks_ct_batch *in, double *d_out, void *stream) {
+  int rc = check_keys(ctx);
+  if (rc || (rc = check_batch(ctx, in, "in"))) return rc;
+  if (in->count && !d_out) return fail(CKKS_EINVAL, "d_out is NULL");
+  if (!in->count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(launch_decrypt(ctx, in->data, in->count, (int)in->level, in->scale, d_out, as_stream(stream)), "decrypt");
+  return CKKS_OK;
+}
+
+int ckks_stream_sync(ckks_ctx *ctx, void *stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)), "stream synchronize");
+  HIP_TRY(hipGetLastError(), "earlier launch");
+  return CKKS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations shared by the C-ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ckks_mi355x.h"
+#include "host_math.hpp"
+
+namespace ckks {
+
+constexpr int kMaxL = 16;
+constexpr int kMaxDigits = 8;
+
+// Per-limb constants passed by value to every kernel.
+struct LimbConsts {
+  int L;                 // limbs of the context
+  int B;                 // Gaussian bound (0 = no noise)
+  uint32_t red_fwd;      // reduction schedule of forward transforms of small inputs
+  uint32_t red_fwd_big;  // ... of forward transforms of canonical residues
+  uint32_t red_inv;      // reduction schedule of inverse transforms
+  double q[kMaxL];
+  double qinv[kMaxL];
+  double ninv[kMaxL];    // N^-1 mod q_i, centered
+  uint64_t qi[kMaxL];
+};
+
+// Device tables owned by a context.
+struct DevTables {
+  double *tw_fwd = nullptr;  // [L][N]
+  double *tw_inv = nullptr;  // [L][N]
+  double *enc_T = nullptr;   // [N] encoding table at scale Delta
+  double *cosj = nullptr;    // [N] cos(pi j / N)
+  uint64_t *cdt = nullptr;   // [kCdtSlots]
+  int64_t *s = nullptr;      // [N] secret key
+  uint64_t *pk = nullptr;    // [2][L][N] public key, coefficient domain
+  double *pk_hat = nullptr;  // [2][L][N] NTT domain times N^-1, centered
+  double *s_hat = nullptr;   // [L][N] NTT domain times N^-1, centered
+};
+
+// What to encrypt: item i has value vals[i] (or px[i]) and Philox index ts[i]
+// (or first_index + i).  With list_count, *list_count items are encrypted: items
+// list[0..*list_count) if `list` is set, else items 0..*list_count-1; without it, 0..n-1.
+struct EncJob {
+  const uint8_t *px = nullptr;
+  const uint32_t *vals = nullptr;
+  const uint64_t *ts = nullptr;
+  const uint32_t *list = nullptr;
+  const uint32_t *list_count = nullptr;
+  uint64_t n = 0;
+  uint64_t first_index = 0;
+  uint64_t seed0 = 0, seed1 = 0;
+  uint64_t *out = nullptr;  // [n][2][L][N]
+};
+
+}  // namespace ckks
+
+struct ckks_ctx {
+  int device = 0;
+  ckks::host::Resolved prm;
+  int N = 0;
+  double scale = 0;
+  int logr = 5;
+  ckks::LimbConsts lc{};
+  ckks::DevTables dev{};
+  std::vector<uint64_t> ninv;  // N^-1 mod q_i
+  bool has_keys = false;
+};
+
+struct ckks_cache {
+  ckks_ctx *ctx = nullptr;
+  int device = 0;
+  int kind = 0;
+  uint32_t base = 0, digits = 0, topk = 0, pool = 0;
+  uint32_t n_slots = 0;           // value entries allocated
+  uint64_t *entries = nullptr;    // [n_slots][2][L][N]
+  uint64_t *pool_cts = nullptr;   // [pool][2][L][N]
+  int16_t *slot_of = nullptr;     // [256] value -> entry slot or -1 (value caches)
+  uint32_t *vals = nullptr;       // [n_slots] value of each entry
+  uint64_t *ts = nullptr;         // [n_slots] Philox index of each entry
+  uint32_t *count = nullptr;      // device: number of valid entries
+};
+
+namespace ckks {
+
+// Launchers (return a hipError_t; enqueue on `stream`).
+hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
+hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream);
+hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream);
+hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
+                          hipStream_t stream);
+
+hipError_t launch_add_sub(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
+                          int level, bool sub, hipStream_t stream);
+hipError_t launch_mul_const(const ckks_ctx *c, const uint64_t *a, uint64_t *out, uint64_t n, int level,
+                            const uint64_t *K, hipStream_t stream);
+hipError_t launch_add_const(const ckks_ctx *c, uint64_t *a, uint64_t n, int level, double scale, const double *d_b,
+                            double b, hipStream_t stream);
+hipError_t launch_rescale(const ckks_ctx *c, const uint64_t *a, uint64_t *out, uint64_t n, int level,
+                          hipStream_t stream);
+hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
+                              uint32_t k, int level, const uint64_t *K, hipStream_t stream);
+
+hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t n, uint32_t topk, uint32_t *hist,
+                                 ckks_cache *cache, hipStream_t stream);
+hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
+                             uint64_t first_index, uint64_t seed0, uint64_t seed1, uint32_t *meta,
+                             uint32_t *miss_list, uint32_t *miss_count, hipStream_t stream);
+hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta, uint64_t n,
+                               uint64_t *out, hipStream_t stream);
+hipError_t launch_radix_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
+                             uint64_t first_index, uint64_t seed0, uint64_t seed1, int16_t *meta, uint32_t *bad,
+                             hipStream_t stream);
+hipError_t launch_radix_gather(const ckks_ctx *c, const ckks_cache *cache, const int16_t *meta, uint64_t n,
+                               uint64_t *out, hipStream_t stream);
+
+// Largest grid the persistent (list-driven) encryption uses.
+constexpr uint64_t kListGrid = 8192;
+
+}  // namespace ckks

@@ -1,0 +1,219 @@
+// Cached encryption (Sec. 3.2) with the randomness of Sec. 3.3.
+//
+// A small metadata pass decides, per pixel, how its ciphertext is assembled (which
+// cache entry, which pool member, which signed radix multiples); the gather kernels
+// then stream the ciphertext rows, reading cache entries that stay resident in the
+// L2 / Infinity Cache and writing each output residue once.  Pixels a value cache
+// does not hold go to a compacted list that the plain encryption kernel consumes.
+#include "internal.hpp"
+#include "modarith.hpp"
+#include "philox.hpp"
+
+namespace ckks {
+
+constexpr int kThreads = 256;
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+// 256-bin histogram of a pixel array (LDS counters per workgroup, then global).
+__global__ void __launch_bounds__(kThreads) k_histogram(const uint8_t *__restrict__ px, uint64_t n, uint32_t *hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads)
+    atomicAdd(&h[px[i]], 1u);
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// Rank of every value by (count descending, value ascending); the first k values that
+// occur become cache slots 0..count-1 with Philox index 256 + value.
+__global__ void __launch_bounds__(256)
+    k_topk(const uint32_t *__restrict__ hist, uint32_t k, int16_t *slot_of, uint32_t *vals, uint64_t *ts,
+           uint32_t *count) {
+  __shared__ uint32_t h[256];
+  const int v = threadIdx.x;
+  h[v] = hist[v];
+  __syncthreads();
+  const uint32_t hv = h[v];
+  uint32_t rank = 0, nz = 0;
+  for (int w = 0; w < 256; w++) {
+    const uint32_t hw = h[w];
+    rank += (hw > hv || (hw == hv && w < v)) ? 1u : 0u;
+    nz += hw > 0 ? 1u : 0u;
+  }
+  if (hv > 0 && rank < k) {
+    slot_of[v] = (int16_t)rank;
+    vals[rank] = (uint32_t)v;
+    ts[rank] = 256 + (uint64_t)v;
+  } else {
+    slot_of[v] = -1;
+  }
+  if (v == 0) *count = nz < k ? nz : k;
+}
+
+// Per pixel t: meta = (slot + 1) | u << 16 for a cached value, with pool member
+// u = floor(npool * w / 2^64) from auxiliary word 0; 0 for a value that is not cached,
+// whose index is appended to the miss list.
+__global__ void __launch_bounds__(kThreads)
+    k_value_meta(const uint8_t *__restrict__ px, uint64_t n, uint64_t first_index, uint64_t s0, uint64_t s1,
+                 const int16_t *__restrict__ slot_of, uint32_t npool, uint32_t *__restrict__ meta,
+                 uint32_t *__restrict__ miss_list, uint32_t *miss_count) {
+  for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
+    const int slot = slot_of[px[t]];
+    if (slot >= 0) {
+      const uint64_t w = philox4x64_10(first_index + t, kTagAux, 0, 0, s0, s1).w[0];
+      const uint32_t u = (uint32_t)mulhi64(w, npool);
+      meta[t] = (uint32_t)(slot + 1) | (u << 16);
+    } else {
+      meta[t] = 0;
+      miss_list[atomicAdd(miss_count, 1u)] = (uint32_t)t;
+    }
+  }
+}
+
+// out row = entry[slot] row + pool[u] row for cached pixels (rows of missed pixels are
+// written by the plain encryption kernel).
+__global__ void __launch_bounds__(kThreads)
+    k_value_gather(const uint64_t *__restrict__ entries, const uint64_t *__restrict__ pool,
+                   const uint32_t *__restrict__ meta, uint64_t rows, int L, int log_n, LimbConsts lc,
+                   uint64_t *__restrict__ out) {
+  const int N = 1 << log_n;
+  const uint64_t S = (uint64_t)2 * L * N;
+  for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const uint64_t ct = row / (uint64_t)(2 * L);
+    const int pl = (int)(row % (uint64_t)(2 * L));
+    const uint32_t m = meta[ct];
+    if (m == 0) continue;
+    const uint64_t q = lc.qi[pl % L];
+    const ulonglong2 *pe = reinterpret_cast<const ulonglong2 *>(entries + (uint64_t)((m & 0xffffu) - 1) * S + (uint64_t)pl * N);
+    const ulonglong2 *pz = reinterpret_cast<const ulonglong2 *>(pool + (uint64_t)(m >> 16) * S + (uint64_t)pl * N);
+    ulonglong2 *po = reinterpret_cast<ulonglong2 *>(out + row * N);
+    for (int i = threadIdx.x; i < N / 2; i += kThreads) {
+      const ulonglong2 a = pe[i], b = pz[i];
+      ulonglong2 z;
+      z.x = add_mod(a.x, b.x, q);
+      z.y = add_mod(a.y, b.y, q);
+      po[i] = z;
+    }
+  }
+}
+
+// Per pixel: signed multiples k_i of the radix entries Enc(r^i) so that
+//   c = Enc(0) + sum_i k_i Enc(r^i),  k_i = d_i + b_i - r * b_{i+1},
+// where d_i are the base-r digits and b_i (i = 1..D-1) bit i-1 of auxiliary word 1:
+// each set bit adds Enc(r^i) and subtracts r copies of Enc(r^(i-1)) (Sec. 3.3).
+__global__ void __launch_bounds__(kThreads)
+    k_radix_meta(const uint8_t *__restrict__ px, uint64_t n, uint64_t first_index, uint64_t s0, uint64_t s1,
+                 uint32_t r, uint32_t D, int16_t *__restrict__ meta, uint32_t *bad) {
+  for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
+    uint32_t p = px[t];
+    const uint64_t aux = philox4x64_10(first_index + t, kTagAux, 0, 0, s0, s1).w[1];
+    int k[kMaxDigits];
+#pragma unroll
+    for (int i = 0; i < kMaxDigits; i++) {
+      k[i] = 0;
+      if ((uint32_t)i < D) {
+        k[i] = (int)(p % r);
+        p /= r;
+      }
+    }
+    if (p != 0) atomicOr(bad, 1u);
+#pragma unroll
+    for (int i = 1; i < kMaxDigits; i++) {
+      if ((uint32_t)i < D && ((aux >> (i - 1)) & 1)) {
+        k[i] += 1;
+        k[i - 1] -= (int)r;
+      }
+    }
+    int16_t *o = meta + t * kMaxDigits;
+#pragma unroll
+    for (int i = 0; i < kMaxDigits; i++) o[i] = (int16_t)k[i];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_radix_gather(const uint64_t *__restrict__ entries, const int16_t *__restrict__ meta, uint64_t rows, int L,
+                   int log_n, uint32_t D, LimbConsts lc, uint64_t *__restrict__ out) {
+  const int N = 1 << log_n;
+  const uint64_t S = (uint64_t)2 * L * N;
+  for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const uint64_t ct = row / (uint64_t)(2 * L);
+    const int pl = (int)(row % (uint64_t)(2 * L));
+    const int l = pl % L;
+    const uint64_t q = lc.qi[l];
+    const double qinv = lc.qinv[l];
+    int k[kMaxDigits];
+#pragma unroll
+    for (int i = 0; i < kMaxDigits; i++) k[i] = meta[ct * kMaxDigits + i];
+    const uint64_t *e0 = entries + (uint64_t)pl * N;
+    uint64_t *po = out + row * N;
+    for (int j = threadIdx.x; j < N; j += kThreads) {
+      int64_t acc = (int64_t)e0[j];
+#pragma unroll
+      for (int i = 0; i < kMaxDigits; i++)
+        if ((uint32_t)i < D) acc += (int64_t)k[i] * (int64_t)e0[(uint64_t)(1 + i) * S + j];
+      po[j] = mod_i64(acc, q, qinv);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static uint32_t grid_for(uint64_t items, uint64_t per_block) {
+  const uint64_t g = (items + per_block - 1) / per_block;
+  return (uint32_t)(g == 0 ? 1 : (g < (1u << 20) ? g : (1u << 20)));
+}
+
+hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t n, uint32_t topk, uint32_t *hist,
+                                 ckks_cache *cache, hipStream_t st) {
+  (void)c;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, hist, 256u, 0u);
+  if (n) hipLaunchKernelGGL(k_histogram, dim3(grid_for(n, 16 * kThreads)), dim3(kThreads), 0, st, px, n, hist);
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, st, hist, topk, cache->slot_of, cache->vals, cache->ts,
+                     cache->count);
+  return hipGetLastError();
+}
+
+hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
+                             uint64_t first_index, uint64_t seed0, uint64_t seed1, uint32_t *meta,
+                             uint32_t *miss_list, uint32_t *miss_count, hipStream_t st) {
+  (void)c;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, miss_count, 1u, 0u);
+  hipLaunchKernelGGL(k_value_meta, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, px, n, first_index, seed0,
+                     seed1, cache->slot_of, cache->pool, meta, miss_list, miss_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta, uint64_t n,
+                               uint64_t *out, hipStream_t st) {
+  const int L = c->prm.L;
+  const uint64_t rows = n * 2 * (uint64_t)L;
+  hipLaunchKernelGGL(k_value_gather, dim3(grid_for(rows, 1)), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
+                     meta, rows, L, c->prm.log_n, c->lc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
+                             uint64_t first_index, uint64_t seed0, uint64_t seed1, int16_t *meta, uint32_t *bad,
+                             hipStream_t st) {
+  (void)c;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, bad, 1u, 0u);
+  hipLaunchKernelGGL(k_radix_meta, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, px, n, first_index, seed0,
+                     seed1, cache->base, cache->digits, meta, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_gather(const ckks_ctx *c, const ckks_cache *cache, const int16_t *meta, uint64_t n,
+                               uint64_t *out, hipStream_t st) {
+  const int L = c->prm.L;
+  const uint64_t rows = n * 2 * (uint64_t)L;
+  hipLaunchKernelGGL(k_radix_gather, dim3(grid_for(rows, 1)), dim3(kThreads), 0, st, cache->entries, meta, rows, L,
+                     c->prm.log_n, cache->digits, c->lc, out);
+  return hipGetLastError();
+}
+
+}  // namespace ckks

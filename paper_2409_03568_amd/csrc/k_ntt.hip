@@ -1,0 +1,323 @@
+// NTT-based kernels: key generation, key preparation, fused per-pixel encryption and
+// decryption.  One workgroup handles one ciphertext at a time (all limbs), so the
+// random polynomials v, e0, e1 are drawn once per ciphertext and reused by every limb.
+#include "internal.hpp"
+#include "ntt.hpp"
+#include "philox.hpp"
+
+namespace ckks {
+
+template <int LOGN, int LOGR>
+struct Shape : NttShape<LOGN, LOGR> {
+  static constexpr int LAST = NttShape<LOGN, LOGR>::NPASS - 1;
+  // dynamic LDS: N doubles of exchange space, the Gaussian table, and a reduction area
+  static constexpr size_t lds_bytes = sizeof(double) * ((size_t)(1 << LOGN) + kCdtSlots + 64);
+};
+
+// Draw the packed samples of one polynomial triple into LDS and read them back in
+// the first-pass layout: smp[r] holds coefficient tid + T*r as
+// (t1 + 1) | (g2 + B) << 8 | (g3 + B) << 16, where t1 is the ternary value of stream
+// tag1 and g2, g3 the Gaussian values of streams tag2, tag3 (all at Philox index t).
+template <int LOGN, int LOGR>
+__device__ __forceinline__ void draw_samples(uint32_t (&smp)[1 << LOGR], uint32_t *lds32, const uint64_t *cdt,
+                                             int B, int tid, uint64_t k0, uint64_t k1, uint64_t t, uint32_t tag1,
+                                             uint32_t tag2, uint32_t tag3) {
+  using S = NttShape<LOGN, LOGR>;
+  static_assert(S::R >= 4, "each thread draws whole Philox blocks");
+#pragma unroll
+  for (int kk = 0; kk < S::R / 4; kk++) {
+    const uint32_t b = (uint32_t)(tid + S::T * kk);
+    const Philox4 pv = philox4x64_10(t, tag1, b, 0, k0, k1);
+    const Philox4 pa = philox4x64_10(t, tag2, b, 0, k0, k1);
+    const Philox4 pb = philox4x64_10(t, tag3, b, 0, k0, k1);
+    uint4 packed;
+    uint32_t *pw = reinterpret_cast<uint32_t *>(&packed);
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      const uint32_t tv = (uint32_t)(ternary_of(pv.w[w]) + 1);
+      const uint32_t ga = (uint32_t)(gauss_of(pa.w[w], cdt, B) + B);
+      const uint32_t gb = (uint32_t)(gauss_of(pb.w[w], cdt, B) + B);
+      pw[w] = tv | (ga << 8) | (gb << 16);
+    }
+    reinterpret_cast<uint4 *>(lds32)[b] = packed;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < S::R; r++) smp[r] = lds32[tid + S::T * r];
+}
+
+__device__ __forceinline__ int smp_t(uint32_t s) { return (int)(s & 0xffu) - 1; }
+__device__ __forceinline__ int smp_g(uint32_t s, int shift, int B) { return (int)((s >> shift) & 0xffu) - B; }
+
+// ---------------------------------------------------------------------------
+// fused plain encryption: per ciphertext, per limb
+//   x = NTT(v); c0 = INTT(x * pk0^) + e0 + m; c1 = INTT(x * pk1^) + e1
+// ---------------------------------------------------------------------------
+template <int LOGN, int LOGR>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_encrypt(EncJob job, LimbConsts lc, DevTables dt) {
+  using S = Shape<LOGN, LOGR>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  extern __shared__ double lds[];
+  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N);
+  uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
+  const int L = lc.L, B = lc.B;
+  const uint64_t count = job.list_count ? (uint64_t)*job.list_count : job.n;
+  for (uint64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    const uint64_t item = job.list ? (uint64_t)job.list[it] : it;
+    const uint64_t t = job.ts ? job.ts[item] : job.first_index + item;
+    const double value = job.vals ? (double)job.vals[item] : (double)job.px[item];
+    uint64_t *out = job.out + item * (uint64_t)(2 * L) * N;
+    __syncthreads();
+    uint32_t smp[R];
+    draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, tid, job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
+    for (int l = 0; l < L; l++) {
+      const double q = lc.q[l], qinv = lc.qinv[l];
+      double x[R];
+#pragma unroll
+      for (int r = 0; r < R; r++) x[r] = (double)smp_t(smp[r]);
+      ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, lc.red_fwd);
+#pragma unroll
+      for (int poly = 0; poly < 2; poly++) {
+        const double *pkh = dt.pk_hat + ((size_t)poly * L + l) * N;
+        double y[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) y[r] = mulmod(x[r], pkh[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
+        ntt_inverse<LOGN, LOGR>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, lc.red_inv);
+        uint64_t *dst = out + ((size_t)poly * L + l) * N;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const int j = tid + T * r;
+          double v = y[r] + (double)smp_g(smp[r], poly == 0 ? 8 : 16, B);
+          if (poly == 0) v += __builtin_rint(value * dt.enc_T[j]);
+          dst[j] = (uint64_t)canon(v, q, qinv);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// key generation, one workgroup per limb l: pk0_l = -a_l * s + e, pk1_l = a_l
+// ---------------------------------------------------------------------------
+template <int LOGN, int LOGR>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_keygen(uint64_t k0, uint64_t k1, LimbConsts lc, DevTables dt) {
+  using S = Shape<LOGN, LOGR>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  extern __shared__ double lds[];
+  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N);
+  uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
+  __syncthreads();
+  const int L = lc.L, B = lc.B, l = blockIdx.x;
+  const double q = lc.q[l], qinv = lc.qinv[l];
+  const uint64_t qi = lc.qi[l];
+  uint32_t smp[R];
+  // s from tag 16 (ternary), e from tag 17 (Gaussian); the third stream is unused
+  draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, tid, k0, k1, 0, kTagSk, kTagEk, kTagEk);
+  // a_l: uniform residues by rejection, coefficient j tries block j, then N + j, ...
+  // accept w < q * floor(2^64 / q) = 2^64 - (2^64 mod q)
+  const uint64_t limit = 0ULL - ((~0ULL % qi + 1) % qi);
+  double a[R];
+  uint64_t *pk1 = dt.pk + ((size_t)L + l) * N;
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const uint32_t j = (uint32_t)(tid + T * r);
+    uint64_t val = 0;
+    bool done = false;
+    for (uint64_t att = 0; !done; att++) {
+      const Philox4 w = philox4x64_10(0, kTagA0 + (uint32_t)l, att * N + j, 0, k0, k1);
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (!done && w.w[k] < limit) {
+          val = w.w[k] % qi;
+          done = true;
+        }
+      }
+    }
+    pk1[j] = val;
+    a[r] = (double)val;
+  }
+  if (l == 0) {
+#pragma unroll
+    for (int r = 0; r < R; r++) dt.s[tid + T * r] = smp_t(smp[r]);
+  }
+  // s_hat * N^-1 for this limb
+  double x[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) x[r] = (double)smp_t(smp[r]);
+  ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, lc.red_fwd);
+  const double ninv = lc.ninv[l];
+#pragma unroll
+  for (int r = 0; r < R; r++) x[r] = reduce(mulmod(x[r], ninv, q, qinv), q, qinv);
+  ntt_forward<LOGN, LOGR>(a, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, lc.red_fwd_big);
+#pragma unroll
+  for (int r = 0; r < R; r++) a[r] = mulmod(a[r], x[r], q, qinv);
+  ntt_inverse<LOGN, LOGR>(a, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, lc.red_inv);
+  uint64_t *pk0 = dt.pk + (size_t)l * N;
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const double e = (double)smp_g(smp[r], 8, B);
+    pk0[tid + T * r] = (uint64_t)canon(e - a[r], q, qinv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// NTT-domain key copies used by encryption and decryption:
+//   blockIdx.y = 0: s_hat_l * N^-1;  1: pk0_hat_l * N^-1;  2: pk1_hat_l * N^-1
+// ---------------------------------------------------------------------------
+template <int LOGN, int LOGR>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keys_prepare(LimbConsts lc, DevTables dt) {
+  using S = Shape<LOGN, LOGR>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, l = blockIdx.x, which = blockIdx.y, L = lc.L;
+  const double q = lc.q[l], qinv = lc.qinv[l];
+  double x[R];
+  if (which == 0) {
+#pragma unroll
+    for (int r = 0; r < R; r++) x[r] = (double)dt.s[tid + T * r];
+  } else {
+    const uint64_t *src = dt.pk + ((size_t)(which - 1) * L + l) * N;
+#pragma unroll
+    for (int r = 0; r < R; r++) x[r] = (double)src[tid + T * r];
+  }
+  ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, which == 0 ? lc.red_fwd : lc.red_fwd_big);
+  double *dst = which == 0 ? dt.s_hat + (size_t)l * N : dt.pk_hat + ((size_t)(which - 1) * L + l) * N;
+#pragma unroll
+  for (int r = 0; r < R; r++)
+    dst[elem_index<LOGN, LOGR, S::LAST>(tid, r)] = reduce(mulmod(x[r], lc.ninv[l], q, qinv), q, qinv);
+}
+
+// ---------------------------------------------------------------------------
+// decryption of limb 0 and decoding of slot 0:
+//   d = c0 + INTT(NTT(c1) * s_hat); out = sum_j center(d_j) cos(pi j/N) / scale
+// ---------------------------------------------------------------------------
+template <int LOGN, int LOGR>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_decrypt(const uint64_t *__restrict__ cts, uint64_t n, int level, double inv_scale, double *__restrict__ out,
+              LimbConsts lc, DevTables dt) {
+  using S = Shape<LOGN, LOGR>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  extern __shared__ double lds[];
+  double *red = lds + N + kCdtSlots;
+  const int tid = threadIdx.x;
+  const double q = lc.q[0], qinv = lc.qinv[0];
+  for (uint64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const uint64_t *c0 = cts + i * (uint64_t)(2 * level) * N;
+    const uint64_t *c1 = c0 + (size_t)level * N;
+    double x[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) x[r] = (double)c1[tid + T * r];
+    ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd, q, qinv, lc.red_fwd_big);
+#pragma unroll
+    for (int r = 0; r < R; r++) x[r] = mulmod(x[r], dt.s_hat[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
+    ntt_inverse<LOGN, LOGR>(x, lds, tid, dt.tw_inv, q, qinv, lc.red_inv);
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int j = tid + T * r;
+      const double d = center(x[r] + (double)c0[j], q, qinv);
+      acc = __builtin_fma(d, dt.cosj[j], acc);
+    }
+    // workgroup sum in a fixed order: wave butterflies, then the waves in sequence
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < T / 64; w++) s += red[w];
+      out[i] = s * inv_scale;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int LOGN, int LOGR, typename F>
+static hipError_t set_lds(F kernel) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)Shape<LOGN, LOGR>::lds_bytes);
+}
+
+template <int LOGN, int LOGR>
+static hipError_t encrypt_t(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
+  using S = Shape<LOGN, LOGR>;
+  hipError_t e = set_lds<LOGN, LOGR>(k_encrypt<LOGN, LOGR>);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_encrypt<LOGN, LOGR>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, job, c->lc, c->dev);
+  return hipGetLastError();
+}
+
+template <int LOGN, int LOGR>
+static hipError_t keygen_t(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
+  using S = Shape<LOGN, LOGR>;
+  hipError_t e = set_lds<LOGN, LOGR>(k_keygen<LOGN, LOGR>);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_keygen<LOGN, LOGR>), dim3(c->lc.L), dim3(S::T), S::lds_bytes, st, s0, s1, c->lc, c->dev);
+  return hipGetLastError();
+}
+
+template <int LOGN, int LOGR>
+static hipError_t prepare_t(const ckks_ctx *c, hipStream_t st) {
+  using S = Shape<LOGN, LOGR>;
+  hipError_t e = set_lds<LOGN, LOGR>(k_keys_prepare<LOGN, LOGR>);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_keys_prepare<LOGN, LOGR>), dim3(c->lc.L, 3), dim3(S::T), S::lds_bytes, st, c->lc, c->dev);
+  return hipGetLastError();
+}
+
+template <int LOGN, int LOGR>
+static hipError_t decrypt_t(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
+                            hipStream_t st) {
+  using S = Shape<LOGN, LOGR>;
+  hipError_t e = set_lds<LOGN, LOGR>(k_decrypt<LOGN, LOGR>);
+  if (e != hipSuccess) return e;
+  const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
+  hipLaunchKernelGGL((k_decrypt<LOGN, LOGR>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, cts, n, level,
+                     1.0 / scale, out, c->lc, c->dev);
+  return hipGetLastError();
+}
+
+// LOGR = 5 (32 values per thread) throughout; N = 2^11 .. 2^14 use 64 .. 512 threads.
+#define CKKS_DISPATCH(CALL)                       \
+  switch (c->prm.log_n) {                         \
+    case 11: return CALL(11, 5);                  \
+    case 12: return CALL(12, 5);                  \
+    case 13: return CALL(13, 5);                  \
+    case 14: return CALL(14, 5);                  \
+    default: return hipErrorInvalidValue;         \
+  }
+
+hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream) {
+#define CALL_ENC(a, b) encrypt_t<a, b>(c, job, grid, stream)
+  CKKS_DISPATCH(CALL_ENC)
+#undef CALL_ENC
+}
+
+hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream) {
+#define CALL_KG(a, b) keygen_t<a, b>(c, seed0, seed1, stream)
+  CKKS_DISPATCH(CALL_KG)
+#undef CALL_KG
+}
+
+hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream) {
+#define CALL_KP(a, b) prepare_t<a, b>(c, stream)
+  CKKS_DISPATCH(CALL_KP)
+#undef CALL_KP
+}
+
+hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
+                          hipStream_t stream) {
+#define CALL_DEC(a, b) decrypt_t<a, b>(c, cts, n, level, scale, out, stream)
+  CKKS_DISPATCH(CALL_DEC)
+#undef CALL_DEC
+}
+
+}  // namespace ckks

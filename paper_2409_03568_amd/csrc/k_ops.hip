@@ -1,0 +1,308 @@
+// Elementwise homomorphic operations (Sec. 2.2.3) and the fused mean filter (Sec. 4.4.1)
+// on canonical uint64 residues.  All of these are bound by HBM bandwidth: each kernel
+// streams its ciphertexts once with 16-byte accesses, one workgroup per N-coefficient
+// row ([ct][poly][limb] rows), and keeps the per-limb constants in registers.
+#include "internal.hpp"
+#include "modarith.hpp"
+#include "philox.hpp"
+
+namespace ckks {
+
+constexpr int kRowThreads = 256;
+
+struct RowConsts {
+  uint64_t q[kMaxL];
+  uint64_t K[kMaxL];   // multiplier per limb
+  uint64_t Kp[kMaxL];  // its Shoup companion
+};
+
+// out = a +/- b, rows of N residues; row r has limb r % level.
+template <bool SUB>
+__global__ void __launch_bounds__(kRowThreads)
+    k_add_sub(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b, uint64_t *__restrict__ out,
+              uint64_t rows, int level, int log_n, RowConsts rc) {
+  const int N = 1 << log_n;
+  for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const uint64_t q = rc.q[row % (uint64_t)level];
+    const ulonglong2 *pa = reinterpret_cast<const ulonglong2 *>(a + row * N);
+    const ulonglong2 *pb = reinterpret_cast<const ulonglong2 *>(b + row * N);
+    ulonglong2 *po = reinterpret_cast<ulonglong2 *>(out + row * N);
+    for (int i = threadIdx.x; i < N / 2; i += kRowThreads) {
+      const ulonglong2 x = pa[i], y = pb[i];
+      ulonglong2 z;
+      z.x = SUB ? sub_mod(x.x, y.x, q) : add_mod(x.x, y.x, q);
+      z.y = SUB ? sub_mod(x.y, y.y, q) : add_mod(x.y, y.y, q);
+      po[i] = z;
+    }
+  }
+}
+
+// out = K_limb * a (Shoup multiplication by the per-limb constant).
+__global__ void __launch_bounds__(kRowThreads)
+    k_mul_const(const uint64_t *__restrict__ a, uint64_t *__restrict__ out, uint64_t rows, int level, int log_n,
+                RowConsts rc) {
+  const int N = 1 << log_n;
+  for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int l = (int)(row % (uint64_t)level);
+    const uint64_t q = rc.q[l], K = rc.K[l], Kp = rc.Kp[l];
+    const ulonglong2 *pa = reinterpret_cast<const ulonglong2 *>(a + row * N);
+    ulonglong2 *po = reinterpret_cast<ulonglong2 *>(out + row * N);
+    for (int i = threadIdx.x; i < N / 2; i += kRowThreads) {
+      const ulonglong2 x = pa[i];
+      ulonglong2 z;
+      z.x = mul_shoup(x.x, K, Kp, q);
+      z.y = mul_shoup(x.y, K, Kp, q);
+      po[i] = z;
+    }
+  }
+}
+
+// c0 += encode(b) at scale `scale` (slot 0): m_j = rint(f cos(pi j / N)), f = (b*scale) 2^(1-log_n).
+// Rows are the c0 rows only: row r is ciphertext r / level, limb r % level.
+__global__ void __launch_bounds__(kRowThreads)
+    k_add_const(uint64_t *__restrict__ a, uint64_t rows, int level, int log_n, double scale,
+                const double *__restrict__ d_b, double b, const double *__restrict__ cosj, LimbConsts lc) {
+  const int N = 1 << log_n;
+  for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const uint64_t ct = row / (uint64_t)level;
+    const int l = (int)(row % (uint64_t)level);
+    const double bb = d_b ? d_b[ct] : b;
+    const double f = ldexp(bb * scale, 1 - log_n);
+    const double q = lc.q[l], qinv = lc.qinv[l];
+    const uint64_t qi = lc.qi[l];
+    uint64_t *c0 = a + (ct * 2 * (uint64_t)level + (uint64_t)l) * N;
+    const bool small = fabs(f) < 4503599627370496.0;  // then |m_j| < 2^52: exact FP64 residue
+    for (int j = threadIdx.x; j < N; j += kRowThreads) {
+      const double m = __builtin_rint(f * cosj[j]);
+      const uint64_t r = small ? (uint64_t)canon(m, q, qinv) : residue_of_double(m, qi, qinv);
+      c0[j] = add_mod(c0[j], r, qi);
+    }
+  }
+}
+
+// Rescale by q_last = q_{level-1}: r = (c_last + h) mod q_last, h = floor(q_last/2);
+// c'_i = (c_i + h - r) * q_last^-1 mod q_i for i < level-1.  One thread per coefficient.
+struct RescaleConsts {
+  uint64_t q[kMaxL];
+  uint64_t h_mod[kMaxL];    // h mod q_i
+  uint64_t qlinv[kMaxL];    // q_last^-1 mod q_i
+  uint64_t qlinv_p[kMaxL];  // Shoup companion
+  uint64_t qlast, h;
+};
+
+__global__ void __launch_bounds__(kRowThreads)
+    k_rescale(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t polys, int level, int log_n,
+              RescaleConsts rc) {
+  const int N = 1 << log_n;
+  const int nl = level - 1;
+  for (uint64_t p = blockIdx.x; p < polys; p += gridDim.x) {
+    const uint64_t *src = in + p * (uint64_t)level * N;
+    uint64_t *dst = out + p * (uint64_t)nl * N;
+    for (int j = threadIdx.x; j < N; j += kRowThreads) {
+      const uint64_t r = add_mod(src[(size_t)nl * N + j], rc.h, rc.qlast);
+      for (int i = 0; i < nl; i++) {
+        const uint64_t qi = rc.q[i];
+        const uint64_t ri = r >= qi ? r - qi : r;  // r < q_last < 2 q_i
+        const uint64_t num = sub_mod(add_mod(src[(size_t)i * N + j], rc.h_mod[i], qi), ri, qi);
+        dst[(size_t)i * N + j] = mul_shoup(num, rc.qlinv[i], rc.qlinv_p[i], qi);
+      }
+    }
+  }
+}
+
+// Fused k x k mean filter with clamped borders: out(y,x) = rescale(K * sum of the window).
+// Thread (x, poly, j) walks down the image keeping the horizontal window sums of the
+// last k rows in a ring, so every input residue is loaded k times (from L2) and read
+// from HBM once; the vertical sum is updated by adding the new row and subtracting the
+// row that leaves (exact modular arithmetic, so the order does not matter).
+struct FilterConsts {
+  uint64_t q[kMaxL];
+  uint64_t K[kMaxL], Kp[kMaxL];          // multiplier K = rint(q_last / k^2) mod q_i
+  uint64_t h_mod[kMaxL];                 // floor(q_last/2) mod q_i
+  uint64_t qlinv[kMaxL], qlinv_p[kMaxL];  // q_last^-1 mod q_i
+  uint64_t qlast, h;
+};
+
+template <int KW, int LV>
+__global__ void __launch_bounds__(kRowThreads)
+    k_mean_filter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t H, uint32_t W, int log_n,
+                  FilterConsts fc) {
+  constexpr int RAD = KW / 2;
+  const int N = 1 << log_n;
+  const uint64_t gid = (uint64_t)blockIdx.x * kRowThreads + threadIdx.x;
+  const int j = (int)(gid & (uint64_t)(N - 1));
+  const uint64_t rest = gid >> log_n;
+  const int poly = (int)(rest & 1);
+  const uint64_t x = rest >> 1;
+  if (x >= W) return;
+  uint32_t xs[KW];
+#pragma unroll
+  for (int d = 0; d < KW; d++) {
+    const int64_t xx = (int64_t)x + d - RAD;
+    xs[d] = (uint32_t)(xx < 0 ? 0 : (xx >= (int64_t)W ? W - 1 : xx));
+  }
+  const uint64_t ct_stride = (uint64_t)2 * LV * N;
+  const uint64_t base = (uint64_t)poly * LV * N + j;
+  auto hsum = [&](int64_t yy, uint64_t (&h)[LV]) {
+    const uint64_t y = (uint64_t)(yy < 0 ? 0 : (yy >= (int64_t)H ? H - 1 : yy));
+#pragma unroll
+    for (int i = 0; i < LV; i++) h[i] = 0;
+#pragma unroll
+    for (int d = 0; d < KW; d++) {
+      const uint64_t *p = in + (y * W + xs[d]) * ct_stride + base;
+#pragma unroll
+      for (int i = 0; i < LV; i++) h[i] = add_mod(h[i], p[(size_t)i * N], fc.q[i]);
+    }
+  };
+  uint64_t ring[KW][LV];
+  uint64_t v[LV];
+#pragma unroll
+  for (int i = 0; i < LV; i++) v[i] = 0;
+#pragma unroll
+  for (int d = 0; d < KW; d++) {
+    hsum((int64_t)d - RAD, ring[d]);
+#pragma unroll
+    for (int i = 0; i < LV; i++) v[i] = add_mod(v[i], ring[d][i], fc.q[i]);
+  }
+  const uint64_t out_stride = (uint64_t)2 * (LV - 1) * N;
+  const uint64_t out_base = (uint64_t)poly * (LV - 1) * N + j;
+  for (uint32_t y0 = 0; y0 < H; y0 += KW) {
+#pragma unroll
+    for (int s = 0; s < KW; s++) {
+      const uint32_t y = y0 + s;
+      if (y >= H) break;
+      // emit row y: multiply by K, then rescale by q_last
+      uint64_t m[LV];
+#pragma unroll
+      for (int i = 0; i < LV; i++) m[i] = mul_shoup(v[i], fc.K[i], fc.Kp[i], fc.q[i]);
+      const uint64_t r = add_mod(m[LV - 1], fc.h, fc.qlast);
+      uint64_t *o = out + ((uint64_t)y * W + x) * out_stride + out_base;
+#pragma unroll
+      for (int i = 0; i < LV - 1; i++) {
+        const uint64_t qi = fc.q[i];
+        const uint64_t ri = r >= qi ? r - qi : r;
+        const uint64_t num = sub_mod(add_mod(m[i], fc.h_mod[i], qi), ri, qi);
+        o[(size_t)i * N] = mul_shoup(num, fc.qlinv[i], fc.qlinv_p[i], qi);
+      }
+      // slide the window: ring slot s holds row y - RAD; replace it by row y + RAD + 1
+      if (y + 1 < H) {
+        uint64_t nh[LV];
+        hsum((int64_t)y + RAD + 1, nh);
+#pragma unroll
+        for (int i = 0; i < LV; i++) {
+          v[i] = add_mod(sub_mod(v[i], ring[s][i], fc.q[i]), nh[i], fc.q[i]);
+          ring[s][i] = nh[i];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static uint32_t row_grid(uint64_t rows) { return (uint32_t)(rows < (1u << 24) ? rows : (1u << 24)); }
+
+hipError_t launch_add_sub(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
+                          int level, bool sub, hipStream_t st) {
+  RowConsts rc{};
+  for (int i = 0; i < level; i++) rc.q[i] = c->prm.q[(size_t)i];
+  const uint64_t rows = n * 2 * (uint64_t)level;
+  if (sub)
+    hipLaunchKernelGGL(k_add_sub<true>, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, b, out, rows, level,
+                       c->prm.log_n, rc);
+  else
+    hipLaunchKernelGGL(k_add_sub<false>, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, b, out, rows, level,
+                       c->prm.log_n, rc);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul_const(const ckks_ctx *c, const uint64_t *a, uint64_t *out, uint64_t n, int level,
+                            const uint64_t *K, hipStream_t st) {
+  RowConsts rc{};
+  for (int i = 0; i < level; i++) {
+    rc.q[i] = c->prm.q[(size_t)i];
+    rc.K[i] = K[i];
+    rc.Kp[i] = host::shoup_companion(K[i], rc.q[i]);
+  }
+  const uint64_t rows = n * 2 * (uint64_t)level;
+  hipLaunchKernelGGL(k_mul_const, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, out, rows, level, c->prm.log_n,
+                     rc);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_const(const ckks_ctx *c, uint64_t *a, uint64_t n, int level, double scale, const double *d_b,
+                            double b, hipStream_t st) {
+  const uint64_t rows = n * (uint64_t)level;
+  hipLaunchKernelGGL(k_add_const, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, rows, level, c->prm.log_n, scale,
+                     d_b, b, c->dev.cosj, c->lc);
+  return hipGetLastError();
+}
+
+static void rescale_consts(const ckks_ctx *c, int level, uint64_t *q, uint64_t *h_mod, uint64_t *qlinv,
+                           uint64_t *qlinv_p, uint64_t *qlast, uint64_t *h) {
+  *qlast = c->prm.q[(size_t)level - 1];
+  *h = *qlast / 2;
+  for (int i = 0; i < level - 1; i++) {
+    q[i] = c->prm.q[(size_t)i];
+    h_mod[i] = *h % q[i];
+    qlinv[i] = host::inv_mod(*qlast % q[i], q[i]);
+    qlinv_p[i] = host::shoup_companion(qlinv[i], q[i]);
+  }
+}
+
+hipError_t launch_rescale(const ckks_ctx *c, const uint64_t *a, uint64_t *out, uint64_t n, int level,
+                          hipStream_t st) {
+  RescaleConsts rc{};
+  rescale_consts(c, level, rc.q, rc.h_mod, rc.qlinv, rc.qlinv_p, &rc.qlast, &rc.h);
+  const uint64_t polys = n * 2;
+  hipLaunchKernelGGL(k_rescale, dim3(row_grid(polys)), dim3(kRowThreads), 0, st, a, out, polys, level, c->prm.log_n,
+                     rc);
+  return hipGetLastError();
+}
+
+template <int KW, int LV>
+static hipError_t filter_t(const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, int log_n,
+                           const FilterConsts &fc, hipStream_t st) {
+  const uint64_t threads = (uint64_t)W * 2 * ((uint64_t)1 << log_n);
+  const uint64_t blocks = (threads + kRowThreads - 1) / kRowThreads;
+  hipLaunchKernelGGL((k_mean_filter<KW, LV>), dim3((uint32_t)blocks), dim3(kRowThreads), 0, st, in, out, H, W, log_n,
+                     fc);
+  return hipGetLastError();
+}
+
+template <int KW>
+static hipError_t filter_level(int level, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, int log_n,
+                               const FilterConsts &fc, hipStream_t st) {
+  switch (level) {
+    case 2: return filter_t<KW, 2>(in, out, H, W, log_n, fc, st);
+    case 3: return filter_t<KW, 3>(in, out, H, W, log_n, fc, st);
+    case 4: return filter_t<KW, 4>(in, out, H, W, log_n, fc, st);
+    case 5: return filter_t<KW, 5>(in, out, H, W, log_n, fc, st);
+    case 6: return filter_t<KW, 6>(in, out, H, W, log_n, fc, st);
+    case 7: return filter_t<KW, 7>(in, out, H, W, log_n, fc, st);
+    case 8: return filter_t<KW, 8>(in, out, H, W, log_n, fc, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
+                              uint32_t k, int level, const uint64_t *K, hipStream_t st) {
+  FilterConsts fc{};
+  for (int i = 0; i < level; i++) {
+    fc.q[i] = c->prm.q[(size_t)i];
+    fc.K[i] = K[i];
+    fc.Kp[i] = host::shoup_companion(K[i], fc.q[i]);
+  }
+  rescale_consts(c, level, fc.q, fc.h_mod, fc.qlinv, fc.qlinv_p, &fc.qlast, &fc.h);
+  const int log_n = c->prm.log_n;
+  switch (k) {
+    case 1: return filter_level<1>(level, in, out, H, W, log_n, fc, st);
+    case 3: return filter_level<3>(level, in, out, H, W, log_n, fc, st);
+    case 5: return filter_level<5>(level, in, out, H, W, log_n, fc, st);
+    case 7: return filter_level<7>(level, in, out, H, W, log_n, fc, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ckks
