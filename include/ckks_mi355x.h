@@ -130,6 +130,13 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out);
 /* Wait for all work of the context and free it.  NULL is ignored. */
 void ckks_context_destroy(ckks_ctx *ctx);
 
+/* Tuning of the NTT kernels (encryption, decryption, keys): each thread of a workgroup
+ * holds values_per_thread ring coefficients (16 or 32), so a workgroup has
+ * N / values_per_thread threads.  Results are identical for every setting; only speed
+ * differs.  CKKS_EINVAL for other values. */
+int ckks_context_set_ntt_width(ckks_ctx *ctx, uint32_t values_per_thread);
+int ckks_context_get_ntt_width(const ckks_ctx *ctx, uint32_t *values_per_thread);
+
 /* Bytes of one ciphertext at `level` (2 * level * N * 8); 0 for a bad level. */
 uint64_t ckks_ct_bytes(const ckks_ctx *ctx, uint32_t level);
 /* Context parameters: N, L, Delta and the primes (host_primes[L], may be NULL). */

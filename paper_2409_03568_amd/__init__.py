@@ -58,6 +58,8 @@ _SIGS = {
     "ckks_context_create": (C.c_int, [C.POINTER(ckks_params_t), C.c_int, C.POINTER(C.c_void_p)]),
     "ckks_context_destroy": (None, [C.c_void_p]),
     "ckks_ct_bytes": (C.c_uint64, [C.c_void_p, C.c_uint32]),
+    "ckks_context_set_ntt_width": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "ckks_context_get_ntt_width": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32)]),
     "ckks_context_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                     C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "ckks_keygen": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
@@ -224,6 +226,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- tuning -------------------------------------------------------------
+    def set_ntt_width(self, values_per_thread: int):
+        _check(lib().ckks_context_set_ntt_width(self.handle, values_per_thread))
+
+    def ntt_width(self) -> int:
+        v = C.c_uint32(0)
+        _check(lib().ckks_context_get_ntt_width(self.handle, C.byref(v)))
+        return int(v.value)
 
     # -- memory -------------------------------------------------------------
     def ct_bytes(self, level: int | None = None) -> int:

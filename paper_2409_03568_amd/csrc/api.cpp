@@ -199,12 +199,10 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
     std::copy(f.begin(), f.end(), twf.begin() + (size_t)i * N);
     std::copy(iv.begin(), iv.end(), twi.begin() + (size_t)i * N);
   }
-  // forward transforms start from ternary/Gaussian values (|x| <= 1) or canonical
-  // residues (< q); inverse transforms start from pointwise products of a value below
-  // 2^51 with a reduced key value (<= 3q/4 + 2)
-  lc.red_fwd = host::forward_reduction_mask(r.log_n, qmax, 1.0);
-  lc.red_fwd_big = host::forward_reduction_mask(r.log_n, qmax, qmax);
-  lc.red_inv = host::inverse_reduction_mask(r.log_n, qmax, 0.75 * qmax + 4);
+  // the transforms' lazy-reduction schedule is compiled per class of prime sizes
+  c->rc = qmax < 1099511627776.0 ? 0 : 1;
+  // values per NTT thread: 16 (twice the threads, half the registers) measured faster
+  c->logr = 4;
   hipError_t e = hipSuccess;
   DevTables &d = c->dev;
   if (e == hipSuccess) e = dev_alloc(&d.tw_fwd, (size_t)L * N);
@@ -241,6 +239,22 @@ void ckks_context_destroy(ckks_ctx *ctx) {
   (void)hipDeviceSynchronize();
   free_tables(ctx);
   delete ctx;
+}
+
+int ckks_context_set_ntt_width(ckks_ctx *ctx, uint32_t values_per_thread) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (values_per_thread != 16 && values_per_thread != 32) return fail(CKKS_EINVAL, "values_per_thread must be 16 or 32");
+  ctx->logr = values_per_thread == 16 ? 4 : 5;
+  return CKKS_OK;
+}
+
+int ckks_context_get_ntt_width(const ckks_ctx *ctx, uint32_t *values_per_thread) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!values_per_thread) return fail(CKKS_EINVAL, "values_per_thread is NULL");
+  *values_per_thread = 1u << ctx->logr;
+  return CKKS_OK;
 }
 
 uint64_t ckks_ct_bytes(const ckks_ctx *ctx, uint32_t level) {

@@ -192,41 +192,5 @@ void twiddles(uint64_t q, uint64_t psi, int log_n, std::vector<double> &fwd, std
   }
 }
 
-// Magnitude bookkeeping for the transforms (all bounds on |value|):
-//   mulmod(a, w) with |w| <= q/2:  |r| <= q/2 + |a| q 2^-53 + 1
-//   reduce(x):                    |r| <= q/2 + 1
-// A stage is followed by a reduction whenever its outputs could exceed 2^51, which keeps
-// every mulmod operand below 2^51 and every intermediate sum below 2^52.
-static const double kLimit = 2251799813685248.0;  // 2^51
-
-uint32_t forward_reduction_mask(int log_n, double qmax, double input_bound) {
-  uint32_t mask = 0;
-  double M = input_bound;
-  for (int s = 0; s < log_n; s++) {
-    const double t = qmax / 2 + M * qmax * ldexp(1.0, -53) + 1;
-    M = M + t;
-    if (M > kLimit) {
-      mask |= 1u << s;
-      M = qmax / 2 + 2;
-    }
-  }
-  return mask;
-}
-
-uint32_t inverse_reduction_mask(int log_n, double qmax, double input_bound) {
-  uint32_t mask = 0;
-  double M = input_bound;
-  for (int s = log_n - 1; s >= 0; s--) {
-    const double prod = qmax / 2 + 2 * M * qmax * ldexp(1.0, -53) + 1;
-    double sum = 2 * M;
-    if (sum > kLimit) {
-      mask |= 1u << s;
-      sum = qmax / 2 + 2;
-    }
-    M = std::max(sum, prod);
-  }
-  return mask;
-}
-
 }  // namespace host
 }  // namespace ckks

@@ -42,11 +42,6 @@ std::vector<double> cos_table(int log_n);
 // fwd[k] = psi^brv(k), inv[k] = psi^-brv(k), k < N.
 void twiddles(uint64_t q, uint64_t psi, int log_n, std::vector<double> &fwd, std::vector<double> &inv);
 
-// Stage masks for the lazy-reduction schedule of the FP64 transforms (bit s set:
-// reduce after stage s), derived from worst-case magnitude bounds for primes <= qmax.
-uint32_t forward_reduction_mask(int log_n, double qmax, double input_bound);
-uint32_t inverse_reduction_mask(int log_n, double qmax, double input_bound);
-
 // Centered double representative of a residue.
 double centered(uint64_t r, uint64_t q);
 

@@ -18,9 +18,6 @@ constexpr int kMaxDigits = 8;
 struct LimbConsts {
   int L;                 // limbs of the context
   int B;                 // Gaussian bound (0 = no noise)
-  uint32_t red_fwd;      // reduction schedule of forward transforms of small inputs
-  uint32_t red_fwd_big;  // ... of forward transforms of canonical residues
-  uint32_t red_inv;      // reduction schedule of inverse transforms
   double q[kMaxL];
   double qinv[kMaxL];
   double ninv[kMaxL];    // N^-1 mod q_i, centered
@@ -62,7 +59,8 @@ struct ckks_ctx {
   ckks::host::Resolved prm;
   int N = 0;
   double scale = 0;
-  int logr = 5;
+  int logr = 5;  // 2^logr values per thread in the NTT kernels (4 or 5)
+  int rc = 1;    // reduction class of the primes: 0 if all q < 2^40, else 1 (q < 2^50)
   ckks::LimbConsts lc{};
   ckks::DevTables dev{};
   std::vector<uint64_t> ninv;  // N^-1 mod q_i

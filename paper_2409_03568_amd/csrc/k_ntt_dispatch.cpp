@@ -1,0 +1,37 @@
+// Selects the per-ring-degree launchers of the NTT path.
+#include "internal.hpp"
+
+namespace ckks {
+
+#define CKKS_DECLARE_RING(LOGN)                                                                              \
+  hipError_t launch_encrypt_##LOGN(const ckks_ctx *, const EncJob &, uint64_t, hipStream_t);                 \
+  hipError_t launch_keygen_##LOGN(const ckks_ctx *, uint64_t, uint64_t, hipStream_t);                        \
+  hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *, hipStream_t);                                      \
+  hipError_t launch_decrypt_##LOGN(const ckks_ctx *, const uint64_t *, uint64_t, int, double, double *, hipStream_t);
+CKKS_DECLARE_RING(11)
+CKKS_DECLARE_RING(12)
+CKKS_DECLARE_RING(13)
+CKKS_DECLARE_RING(14)
+
+#define CKKS_RING_SWITCH(FN, ...)                      \
+  switch (c->prm.log_n) {                              \
+    case 11: return FN##_11(c, __VA_ARGS__);           \
+    case 12: return FN##_12(c, __VA_ARGS__);           \
+    case 13: return FN##_13(c, __VA_ARGS__);           \
+    case 14: return FN##_14(c, __VA_ARGS__);           \
+    default: return hipErrorInvalidValue;              \
+  }
+
+hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream) {
+  CKKS_RING_SWITCH(launch_encrypt, job, grid, stream)
+}
+hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream) {
+  CKKS_RING_SWITCH(launch_keygen, seed0, seed1, stream)
+}
+hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream) { CKKS_RING_SWITCH(launch_keys_prepare, stream) }
+hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
+                          hipStream_t stream) {
+  CKKS_RING_SWITCH(launch_decrypt, cts, n, level, scale, out, stream)
+}
+
+}  // namespace ckks

@@ -1,6 +1,11 @@
 // NTT-based kernels: key generation, key preparation, fused per-pixel encryption and
 // decryption.  One workgroup handles one ciphertext at a time (all limbs), so the
 // random polynomials v, e0, e1 are drawn once per ciphertext and reused by every limb.
+//
+// Template parameters: LOGN (ring degree), LOGR (values per thread, so N / 2^LOGR threads
+// per workgroup) and RC (reduction class of the primes, see ntt.hpp).  Each ring degree is
+// instantiated in its own translation unit (k_ntt_<LOGN>.hip).
+#pragma once
 #include "internal.hpp"
 #include "ntt.hpp"
 #include "philox.hpp"
@@ -10,8 +15,9 @@ namespace ckks {
 template <int LOGN, int LOGR>
 struct Shape : NttShape<LOGN, LOGR> {
   static constexpr int LAST = NttShape<LOGN, LOGR>::NPASS - 1;
-  // dynamic LDS: N doubles of exchange space, the Gaussian table, and a reduction area
-  static constexpr size_t lds_bytes = sizeof(double) * ((size_t)(1 << LOGN) + kCdtSlots + 64);
+  // dynamic LDS: the exchange space (N doubles with padding, see lds_pos), the Gaussian
+  // table, and a reduction area
+  static constexpr size_t lds_bytes = sizeof(double) * ((size_t)(1 << LOGN) * 9 / 8 + kCdtSlots + 64);
 };
 
 // Draw the packed samples of one polynomial triple into LDS and read them back in
@@ -24,7 +30,7 @@ __device__ __forceinline__ void draw_samples(uint32_t (&smp)[1 << LOGR], uint32_
                                              uint32_t tag2, uint32_t tag3) {
   using S = NttShape<LOGN, LOGR>;
   static_assert(S::R >= 4, "each thread draws whole Philox blocks");
-#pragma unroll
+#pragma unroll 1
   for (int kk = 0; kk < S::R / 4; kk++) {
     const uint32_t b = (uint32_t)(tid + S::T * kk);
     const Philox4 pv = philox4x64_10(t, tag1, b, 0, k0, k1);
@@ -53,13 +59,13 @@ __device__ __forceinline__ int smp_g(uint32_t s, int shift, int B) { return (int
 // fused plain encryption: per ciphertext, per limb
 //   x = NTT(v); c0 = INTT(x * pk0^) + e0 + m; c1 = INTT(x * pk1^) + e1
 // ---------------------------------------------------------------------------
-template <int LOGN, int LOGR>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR))
-    k_encrypt(EncJob job, LimbConsts lc, DevTables dt) {
+template <int LOGN, int LOGR, int RC>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_encrypt(EncJob job, LimbConsts lc, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
   extern __shared__ double lds[];
-  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N);
+  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N + N / 8);
   uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
@@ -72,20 +78,21 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     uint64_t *out = job.out + item * (uint64_t)(2 * L) * N;
     __syncthreads();
     uint32_t smp[R];
-    draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, tid, job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
+    draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
     for (int l = 0; l < L; l++) {
       const double q = lc.q[l], qinv = lc.qinv[l];
+      const int tid = opaque(threadIdx.x);
       double x[R];
 #pragma unroll
       for (int r = 0; r < R; r++) x[r] = (double)smp_t(smp[r]);
-      ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, lc.red_fwd);
-#pragma unroll
+      ntt_forward<LOGN, LOGR, Red::fwd_small>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
+#pragma unroll 1
       for (int poly = 0; poly < 2; poly++) {
         const double *pkh = dt.pk_hat + ((size_t)poly * L + l) * N;
         double y[R];
 #pragma unroll
         for (int r = 0; r < R; r++) y[r] = mulmod(x[r], pkh[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
-        ntt_inverse<LOGN, LOGR>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, lc.red_inv);
+        ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv);
         uint64_t *dst = out + ((size_t)poly * L + l) * N;
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -102,13 +109,13 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 // ---------------------------------------------------------------------------
 // key generation, one workgroup per limb l: pk0_l = -a_l * s + e, pk1_l = a_l
 // ---------------------------------------------------------------------------
-template <int LOGN, int LOGR>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR))
-    k_keygen(uint64_t k0, uint64_t k1, LimbConsts lc, DevTables dt) {
+template <int LOGN, int LOGR, int RC>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keygen(uint64_t k0, uint64_t k1, LimbConsts lc, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
   extern __shared__ double lds[];
-  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N);
+  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N + N / 8);
   uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
@@ -150,14 +157,14 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   double x[R];
 #pragma unroll
   for (int r = 0; r < R; r++) x[r] = (double)smp_t(smp[r]);
-  ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, lc.red_fwd);
+  ntt_forward<LOGN, LOGR, Red::fwd_small>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
   const double ninv = lc.ninv[l];
 #pragma unroll
   for (int r = 0; r < R; r++) x[r] = reduce(mulmod(x[r], ninv, q, qinv), q, qinv);
-  ntt_forward<LOGN, LOGR>(a, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, lc.red_fwd_big);
+  ntt_forward<LOGN, LOGR, Red::fwd_big>(a, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
 #pragma unroll
   for (int r = 0; r < R; r++) a[r] = mulmod(a[r], x[r], q, qinv);
-  ntt_inverse<LOGN, LOGR>(a, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, lc.red_inv);
+  ntt_inverse<LOGN, LOGR, Red::inv>(a, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv);
   uint64_t *pk0 = dt.pk + (size_t)l * N;
 #pragma unroll
   for (int r = 0; r < R; r++) {
@@ -170,9 +177,10 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 // NTT-domain key copies used by encryption and decryption:
 //   blockIdx.y = 0: s_hat_l * N^-1;  1: pk0_hat_l * N^-1;  2: pk1_hat_l * N^-1
 // ---------------------------------------------------------------------------
-template <int LOGN, int LOGR>
+template <int LOGN, int LOGR, int RC>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keys_prepare(LimbConsts lc, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
   extern __shared__ double lds[];
   const int tid = threadIdx.x, l = blockIdx.x, which = blockIdx.y, L = lc.L;
@@ -181,12 +189,13 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keys_prepare(LimbConsts 
   if (which == 0) {
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = (double)dt.s[tid + T * r];
+    ntt_forward<LOGN, LOGR, Red::fwd_small>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
   } else {
     const uint64_t *src = dt.pk + ((size_t)(which - 1) * L + l) * N;
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = (double)src[tid + T * r];
+    ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
   }
-  ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv, which == 0 ? lc.red_fwd : lc.red_fwd_big);
   double *dst = which == 0 ? dt.s_hat + (size_t)l * N : dt.pk_hat + ((size_t)(which - 1) * L + l) * N;
 #pragma unroll
   for (int r = 0; r < R; r++)
@@ -197,26 +206,28 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keys_prepare(LimbConsts 
 // decryption of limb 0 and decoding of slot 0:
 //   d = c0 + INTT(NTT(c1) * s_hat); out = sum_j center(d_j) cos(pi j/N) / scale
 // ---------------------------------------------------------------------------
-template <int LOGN, int LOGR>
+template <int LOGN, int LOGR, int RC>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     k_decrypt(const uint64_t *__restrict__ cts, uint64_t n, int level, double inv_scale, double *__restrict__ out,
               LimbConsts lc, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
   extern __shared__ double lds[];
-  double *red = lds + N + kCdtSlots;
+  double *red = lds + N + N / 8 + kCdtSlots;
   const int tid = threadIdx.x;
   const double q = lc.q[0], qinv = lc.qinv[0];
   for (uint64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int tid = opaque(threadIdx.x);
     const uint64_t *c0 = cts + i * (uint64_t)(2 * level) * N;
     const uint64_t *c1 = c0 + (size_t)level * N;
     double x[R];
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = (double)c1[tid + T * r];
-    ntt_forward<LOGN, LOGR>(x, lds, tid, dt.tw_fwd, q, qinv, lc.red_fwd_big);
+    ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd, q, qinv);
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = mulmod(x[r], dt.s_hat[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
-    ntt_inverse<LOGN, LOGR>(x, lds, tid, dt.tw_inv, q, qinv, lc.red_inv);
+    ntt_inverse<LOGN, LOGR, Red::inv>(x, lds, tid, dt.tw_inv, q, qinv);
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -238,7 +249,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// launch helpers for one ring degree
 // ---------------------------------------------------------------------------
 template <int LOGN, int LOGR, typename F>
 static hipError_t set_lds(F kernel) {
@@ -246,78 +257,67 @@ static hipError_t set_lds(F kernel) {
                              (int)Shape<LOGN, LOGR>::lds_bytes);
 }
 
-template <int LOGN, int LOGR>
-static hipError_t encrypt_t(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
+template <int LOGN, int LOGR, int RC>
+struct Launch {
   using S = Shape<LOGN, LOGR>;
-  hipError_t e = set_lds<LOGN, LOGR>(k_encrypt<LOGN, LOGR>);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_encrypt<LOGN, LOGR>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, job, c->lc, c->dev);
-  return hipGetLastError();
-}
-
-template <int LOGN, int LOGR>
-static hipError_t keygen_t(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
-  using S = Shape<LOGN, LOGR>;
-  hipError_t e = set_lds<LOGN, LOGR>(k_keygen<LOGN, LOGR>);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_keygen<LOGN, LOGR>), dim3(c->lc.L), dim3(S::T), S::lds_bytes, st, s0, s1, c->lc, c->dev);
-  return hipGetLastError();
-}
-
-template <int LOGN, int LOGR>
-static hipError_t prepare_t(const ckks_ctx *c, hipStream_t st) {
-  using S = Shape<LOGN, LOGR>;
-  hipError_t e = set_lds<LOGN, LOGR>(k_keys_prepare<LOGN, LOGR>);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_keys_prepare<LOGN, LOGR>), dim3(c->lc.L, 3), dim3(S::T), S::lds_bytes, st, c->lc, c->dev);
-  return hipGetLastError();
-}
-
-template <int LOGN, int LOGR>
-static hipError_t decrypt_t(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
-                            hipStream_t st) {
-  using S = Shape<LOGN, LOGR>;
-  hipError_t e = set_lds<LOGN, LOGR>(k_decrypt<LOGN, LOGR>);
-  if (e != hipSuccess) return e;
-  const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
-  hipLaunchKernelGGL((k_decrypt<LOGN, LOGR>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, cts, n, level,
-                     1.0 / scale, out, c->lc, c->dev);
-  return hipGetLastError();
-}
-
-// LOGR = 5 (32 values per thread) throughout; N = 2^11 .. 2^14 use 64 .. 512 threads.
-#define CKKS_DISPATCH(CALL)                       \
-  switch (c->prm.log_n) {                         \
-    case 11: return CALL(11, 5);                  \
-    case 12: return CALL(12, 5);                  \
-    case 13: return CALL(13, 5);                  \
-    case 14: return CALL(14, 5);                  \
-    default: return hipErrorInvalidValue;         \
+  static hipError_t encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR>(k_encrypt<LOGN, LOGR, RC>);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_encrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, job, c->lc,
+                       c->dev);
+    return hipGetLastError();
   }
+  static hipError_t keygen(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR>(k_keygen<LOGN, LOGR, RC>);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_keygen<LOGN, LOGR, RC>), dim3(c->lc.L), dim3(S::T), S::lds_bytes, st, s0, s1, c->lc, c->dev);
+    return hipGetLastError();
+  }
+  static hipError_t prepare(const ckks_ctx *c, hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR>(k_keys_prepare<LOGN, LOGR, RC>);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_keys_prepare<LOGN, LOGR, RC>), dim3(c->lc.L, 3), dim3(S::T), S::lds_bytes, st, c->lc, c->dev);
+    return hipGetLastError();
+  }
+  static hipError_t decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
+                            hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR>(k_decrypt<LOGN, LOGR, RC>);
+    if (e != hipSuccess) return e;
+    const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
+    hipLaunchKernelGGL((k_decrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, cts, n, level,
+                       1.0 / scale, out, c->lc, c->dev);
+    return hipGetLastError();
+  }
+};
 
-hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream) {
-#define CALL_ENC(a, b) encrypt_t<a, b>(c, job, grid, stream)
-  CKKS_DISPATCH(CALL_ENC)
-#undef CALL_ENC
-}
-
-hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream) {
-#define CALL_KG(a, b) keygen_t<a, b>(c, seed0, seed1, stream)
-  CKKS_DISPATCH(CALL_KG)
-#undef CALL_KG
-}
-
-hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream) {
-#define CALL_KP(a, b) prepare_t<a, b>(c, stream)
-  CKKS_DISPATCH(CALL_KP)
-#undef CALL_KP
-}
-
-hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
-                          hipStream_t stream) {
-#define CALL_DEC(a, b) decrypt_t<a, b>(c, cts, n, level, scale, out, stream)
-  CKKS_DISPATCH(CALL_DEC)
-#undef CALL_DEC
-}
+// All launchers of one ring degree, selecting the thread shape (c->logr) and the
+// reduction class (c->rc) at run time.
+template <int LOGN>
+struct RingLaunch {
+  template <typename F>
+  static hipError_t pick(const ckks_ctx *c, F f) {
+    if (c->logr == 4) return c->rc ? f(Launch<LOGN, 4, 1>{}) : f(Launch<LOGN, 4, 0>{});
+    if (c->logr == 5) return c->rc ? f(Launch<LOGN, 5, 1>{}) : f(Launch<LOGN, 5, 0>{});
+    return hipErrorInvalidValue;
+  }
+};
 
 }  // namespace ckks
+
+// Defines the per-ring-degree launcher entry points in one translation unit.
+#define CKKS_DEFINE_RING_LAUNCHERS(LOGN)                                                                            \
+  namespace ckks {                                                                                                  \
+  hipError_t launch_encrypt_##LOGN(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {           \
+    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::encrypt(c, job, grid, st); });                \
+  }                                                                                                                 \
+  hipError_t launch_keygen_##LOGN(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {                    \
+    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::keygen(c, s0, s1, st); });                    \
+  }                                                                                                                 \
+  hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *c, hipStream_t st) {                                        \
+    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::prepare(c, st); });                           \
+  }                                                                                                                 \
+  hipError_t launch_decrypt_##LOGN(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale,     \
+                                   double *out, hipStream_t st) {                                                   \
+    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::decrypt(c, cts, n, level, scale, out, st); }); \
+  }                                                                                                                 \
+  }

@@ -15,6 +15,12 @@
 // first pass thread `tid` holds elements tid + T*r (so global loads and stores of the
 // coefficient-domain data are coalesced); in the last pass it holds groups of 2^P
 // consecutive elements, which is also where the pointwise product happens.
+//
+// Lazy reduction: values are signed and grow through the stages; a reduction after
+// stage s is compiled in when bit s of the schedule is set.  The schedules are fixed at
+// compile time per reduction class (class 0: primes small enough to need none; class 1:
+// primes below 2^50), derived from worst-case magnitude bounds so that every value stays
+// below 2^51 (see modarith.hpp for the bounds of the primitive operations).
 #pragma once
 #include "modarith.hpp"
 
@@ -30,6 +36,61 @@ struct NttShape {
   static constexpr int len(int p) { return p == NPASS - 1 ? LOGN - p * LOGR : LOGR; }
 };
 
+// ---------------------------------------------------------------------------
+// reduction schedules
+// ---------------------------------------------------------------------------
+// Bounds on magnitudes (q <= qmax):  mulmod(a, w), |w| <= q/2:  |r| <= q/2 + |a| q 2^-53 + 1;
+// reduce(x): |r| <= q/2 + 1.  A stage is followed by a reduction when its outputs could
+// exceed 2^51.  The bounds grow with q, so a schedule derived for qmax serves every
+// smaller prime.
+constexpr double kBoundLimit = 2251799813685248.0;   // 2^51
+constexpr double kTwoPowMinus53 = 1.0 / 9007199254740992.0;
+
+constexpr uint32_t forward_schedule(int log_n, double qmax, double input_bound) {
+  uint32_t mask = 0;
+  double M = input_bound;
+  for (int s = 0; s < log_n; s++) {
+    M = M + (qmax / 2 + M * qmax * kTwoPowMinus53 + 1);
+    if (M > kBoundLimit) {
+      mask |= 1u << s;
+      M = qmax / 2 + 2;
+    }
+  }
+  return mask;
+}
+
+// Inverse: the sum output doubles, the difference output goes through a product; only
+// the sum outputs are reduced.
+constexpr uint32_t inverse_schedule(int log_n, double qmax, double input_bound) {
+  uint32_t mask = 0;
+  double M = input_bound;
+  for (int s = log_n - 1; s >= 0; s--) {
+    const double prod = qmax / 2 + 2 * M * qmax * kTwoPowMinus53 + 1;
+    double sum = 2 * M;
+    if (sum > kBoundLimit) {
+      mask |= 1u << s;
+      sum = qmax / 2 + 2;
+    }
+    M = sum > prod ? sum : prod;
+  }
+  return mask;
+}
+
+// Inputs of the transforms: small signed values (ternary, |x| <= 1), canonical residues
+// (< q), and pointwise products of a value below 2^51 with a reduced key (<= 3q/4 + 2).
+constexpr double kClassQmax[2] = {1099511627776.0 /* 2^40 */, 1125899906842624.0 /* 2^50 */};
+
+template <int LOGN, int RC>
+struct Schedule {
+  static constexpr double qmax = kClassQmax[RC];
+  static constexpr uint32_t fwd_small = forward_schedule(LOGN, qmax, 1.0);
+  static constexpr uint32_t fwd_big = forward_schedule(LOGN, qmax, qmax);
+  static constexpr uint32_t inv = inverse_schedule(LOGN, qmax, 0.75 * qmax + 4);
+};
+
+// ---------------------------------------------------------------------------
+// layouts
+// ---------------------------------------------------------------------------
 // Element index held in register r by thread tid during pass PASS.
 template <int LOGN, int LOGR, int PASS>
 CKKS_HD int elem_index(int tid, int r) {
@@ -42,10 +103,39 @@ CKKS_HD int elem_index(int tid, int r) {
   return (blk << (LOGN - S0)) + (k << LTLO) + off;
 }
 
-// Forward (Cooley-Tukey) stages of one pass.  red_mask bit s: reduce every value after stage s.
-template <int LOGN, int LOGR, int PASS>
-CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid, const double *__restrict__ tw, double q,
-                                         double qinv, uint32_t red_mask) {
+// LDS position of element e: one padding slot after every 8 elements (N + N/8 slots).
+// The last pass's lanes are 8 elements apart and would otherwise hit the same banks; with
+// the padding they are 9 apart.  Every pass's positions stay affine in the register index
+// (the padding depends only on bits that the register index does not change), so the LDS
+// accesses of one thread share a base address with immediate offsets.
+CKKS_HD int lds_pos(int e) { return e + (e >> 3); }
+
+// ---------------------------------------------------------------------------
+// passes
+// ---------------------------------------------------------------------------
+// Keeps the device scheduler from interleaving consecutive stages: a pass compiles to
+// one straight-line block, and hoisting later stages' loads and arithmetic over earlier
+// ones raises register pressure past what two waves per SIMD can hold.
+// The thread index as a value the compiler cannot prove loop-invariant: address
+// arithmetic derived from it stays next to its use instead of being hoisted out of the
+// per-ciphertext loops, where dozens of precomputed pointers would stay live.
+CKKS_HD int opaque(int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(v));
+#endif
+  return v;
+}
+
+CKKS_HD void stage_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// Forward (Cooley-Tukey) stages of one pass; reduce every value after stage s if bit s of RED.
+template <int LOGN, int LOGR, int PASS, uint32_t RED>
+CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ tw, double q, double qinv) {
+  const int tid = opaque(tid_in);
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;
@@ -63,19 +153,20 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid, const double *__restrict_
         const double W = tw[(1 << s) + (blk << l) + (k >> (P - l))];
         ct_butterfly(x[u * (1 << P) + k], x[u * (1 << P) + k + half], W, q, qinv);
       }
-      if ((red_mask >> s) & 1u) {
+      if ((RED >> s) & 1u) {
 #pragma unroll
         for (int k = 0; k < (1 << P); k++) x[u * (1 << P) + k] = reduce(x[u * (1 << P) + k], q, qinv);
       }
+      stage_fence();
     }
   }
 }
 
-// Inverse (Gentleman-Sande) stages of one pass, in decreasing stage order.
-// red_mask bit s: reduce the sum outputs after stage s.
-template <int LOGN, int LOGR, int PASS>
-CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid, const double *__restrict__ itw, double q,
-                                         double qinv, uint32_t red_mask) {
+// Inverse (Gentleman-Sande) stages of one pass, in decreasing stage order; reduce the sum
+// outputs after stage s if bit s of RED.
+template <int LOGN, int LOGR, int PASS, uint32_t RED>
+CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ itw, double q, double qinv) {
+  const int tid = opaque(tid_in);
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;
@@ -87,7 +178,6 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid, const double *__restrict_
     for (int l = P - 1; l >= 0; l--) {
       const int s = S0 + l;
       const int half = 1 << (P - 1 - l);
-      const bool red = (red_mask >> s) & 1u;
 #pragma unroll
       for (int k = 0; k < (1 << P); k++) {
         if (k & half) continue;
@@ -95,69 +185,72 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid, const double *__restrict_
         double &X = x[u * (1 << P) + k];
         double &Y = x[u * (1 << P) + k + half];
         gs_butterfly(X, Y, W, q, qinv);
-        if (red) X = reduce(X, q, qinv);
+        if ((RED >> s) & 1u) X = reduce(X, q, qinv);
       }
+      stage_fence();
     }
   }
 }
 
 template <int LOGN, int LOGR, int PASS>
-CKKS_HD void lds_store(double *lds, const double (&x)[1 << LOGR], int tid) {
+CKKS_HD void lds_store(double *lds, const double (&x)[1 << LOGR], int tid_in) {
+  const int tid = opaque(tid_in);
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) lds[elem_index<LOGN, LOGR, PASS>(tid, r)] = x[r];
+  for (int r = 0; r < (1 << LOGR); r++) lds[lds_pos(elem_index<LOGN, LOGR, PASS>(tid, r))] = x[r];
 }
 
 template <int LOGN, int LOGR, int PASS>
-CKKS_HD void lds_load(const double *lds, double (&x)[1 << LOGR], int tid) {
+CKKS_HD void lds_load(const double *lds, double (&x)[1 << LOGR], int tid_in) {
+  const int tid = opaque(tid_in);
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) x[r] = lds[elem_index<LOGN, LOGR, PASS>(tid, r)];
+  for (int r = 0; r < (1 << LOGR); r++) x[r] = lds[lds_pos(elem_index<LOGN, LOGR, PASS>(tid, r))];
 }
 
 // Passes 1..NPASS-1 of the forward transform (pass 0 is run by the caller on the
 // first-pass layout); ends with x in the last-pass layout.  Contains barriers: every
 // thread of the workgroup must call it.
-template <int LOGN, int LOGR, int PASS = 1>
+template <int LOGN, int LOGR, uint32_t RED, int PASS = 1>
 __device__ __forceinline__ void fwd_rest(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ tw,
-                                         double q, double qinv, uint32_t red_mask) {
+                                         double q, double qinv) {
   if constexpr (PASS < NttShape<LOGN, LOGR>::NPASS) {
     __syncthreads();
     lds_store<LOGN, LOGR, PASS - 1>(lds, x, tid);
     __syncthreads();
     lds_load<LOGN, LOGR, PASS>(lds, x, tid);
-    fwd_pass<LOGN, LOGR, PASS>(x, tid, tw, q, qinv, red_mask);
-    fwd_rest<LOGN, LOGR, PASS + 1>(x, lds, tid, tw, q, qinv, red_mask);
+    fwd_pass<LOGN, LOGR, PASS, RED>(x, tid, tw, q, qinv);
+    fwd_rest<LOGN, LOGR, RED, PASS + 1>(x, lds, tid, tw, q, qinv);
   }
 }
 
 // Whole forward transform from the first-pass layout to the last-pass layout.
-template <int LOGN, int LOGR>
+template <int LOGN, int LOGR, uint32_t RED>
 __device__ __forceinline__ void ntt_forward(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ tw,
-                                            double q, double qinv, uint32_t red_mask) {
-  fwd_pass<LOGN, LOGR, 0>(x, tid, tw, q, qinv, red_mask);
-  fwd_rest<LOGN, LOGR, 1>(x, lds, tid, tw, q, qinv, red_mask);
+                                            double q, double qinv) {
+  fwd_pass<LOGN, LOGR, 0, RED>(x, tid, tw, q, qinv);
+  fwd_rest<LOGN, LOGR, RED, 1>(x, lds, tid, tw, q, qinv);
 }
 
-template <int LOGN, int LOGR, int PASS>
+template <int LOGN, int LOGR, uint32_t RED, int PASS>
 __device__ __forceinline__ void inv_rest(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
-                                         double q, double qinv, uint32_t red_mask) {
+                                         double q, double qinv) {
   if constexpr (PASS >= 0) {
     __syncthreads();
     lds_store<LOGN, LOGR, PASS + 1>(lds, x, tid);
     __syncthreads();
     lds_load<LOGN, LOGR, PASS>(lds, x, tid);
-    inv_pass<LOGN, LOGR, PASS>(x, tid, itw, q, qinv, red_mask);
-    inv_rest<LOGN, LOGR, PASS - 1>(x, lds, tid, itw, q, qinv, red_mask);
+    inv_pass<LOGN, LOGR, PASS, RED>(x, tid, itw, q, qinv);
+    inv_rest<LOGN, LOGR, RED, PASS - 1>(x, lds, tid, itw, q, qinv);
   }
 }
 
 // Whole inverse transform (without the factor 1/N) from the last-pass layout to the
 // first-pass layout.
-template <int LOGN, int LOGR>
+template <int LOGN, int LOGR, uint32_t RED>
 __device__ __forceinline__ void ntt_inverse(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
-                                            double q, double qinv, uint32_t red_mask) {
+                                            double q, double qinv) {
   constexpr int LAST = NttShape<LOGN, LOGR>::NPASS - 1;
-  inv_pass<LOGN, LOGR, LAST>(x, tid, itw, q, qinv, red_mask);
-  inv_rest<LOGN, LOGR, LAST - 1>(x, lds, tid, itw, q, qinv, red_mask);
+  inv_pass<LOGN, LOGR, LAST, RED>(x, tid, itw, q, qinv);
+  inv_rest<LOGN, LOGR, RED, LAST - 1>(x, lds, tid, itw, q, qinv);
 }
 
 }  // namespace ckks

@@ -2,11 +2,13 @@
 //
 // The per-pass NTT functions, the FP64 modular arithmetic and the Philox samplers of
 // the HIP library are host-callable; this file runs them for one emulated workgroup,
-// thread by thread between the LDS exchanges, so the transforms, their layouts and
-// their lazy-reduction schedule can be checked against the oracle without a GPU.
+// thread by thread between the LDS exchanges, so the transforms, their layouts, the LDS
+// placement and the compiled lazy-reduction schedules can be checked against the oracle
+// without a GPU.
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "../../paper_2409_03568_amd/csrc/host_math.hpp"
@@ -18,56 +20,62 @@ using namespace ckks;
 namespace {
 
 double g_max_abs = 0;
+bool g_lds_bijective = true;
 
-template <int LOGR>
 void track(const std::vector<std::vector<double>> &X) {
   for (auto &v : X)
     for (double d : v) g_max_abs = fmax(g_max_abs, fabs(d));
 }
 
-template <int LOGN, int LOGR>
-void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double qinv, uint32_t mask) {
+template <int LOGN, int LOGR, uint32_t RED>
+void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double qinv) {
   using S = NttShape<LOGN, LOGR>;
-  std::vector<double> lds(S::N);
+  std::vector<double> lds(S::N + S::N / 8);
   double x[S::R];
   for (int t = 0; t < S::T; t++) {
     for (int r = 0; r < S::R; r++) x[r] = X[t][r];
-    fwd_pass<LOGN, LOGR, 0>(x, t, tw, q, qinv, mask);
+    fwd_pass<LOGN, LOGR, 0, RED>(x, t, tw, q, qinv);
     for (int r = 0; r < S::R; r++) X[t][r] = x[r];
   }
-  track<LOGR>(X);
+  track(X);
   auto step = [&](auto pass_c) {
     constexpr int P = decltype(pass_c)::value;
     if constexpr (P >= 1 && P < S::NPASS) {
+      std::vector<int> hit(S::N + S::N / 8, 0);
       for (int t = 0; t < S::T; t++) {
-        for (int r = 0; r < S::R; r++) x[r] = X[t][r];
+        for (int r = 0; r < S::R; r++) {
+          x[r] = X[t][r];
+          hit[lds_pos(elem_index<LOGN, LOGR, P - 1>(t, r))]++;
+        }
         lds_store<LOGN, LOGR, P - 1>(lds.data(), x, t);
       }
+      for (int h : hit) g_lds_bijective = g_lds_bijective && h <= 1;
       for (int t = 0; t < S::T; t++) {
         lds_load<LOGN, LOGR, P>(lds.data(), x, t);
-        fwd_pass<LOGN, LOGR, P>(x, t, tw, q, qinv, mask);
+        fwd_pass<LOGN, LOGR, P, RED>(x, t, tw, q, qinv);
         for (int r = 0; r < S::R; r++) X[t][r] = x[r];
       }
-      track<LOGR>(X);
+      track(X);
     }
   };
   step(std::integral_constant<int, 1>{});
   step(std::integral_constant<int, 2>{});
   step(std::integral_constant<int, 3>{});
+  step(std::integral_constant<int, 4>{});
 }
 
-template <int LOGN, int LOGR>
-void inv(std::vector<std::vector<double>> &X, const double *itw, double q, double qinv, uint32_t mask) {
+template <int LOGN, int LOGR, uint32_t RED>
+void inv(std::vector<std::vector<double>> &X, const double *itw, double q, double qinv) {
   using S = NttShape<LOGN, LOGR>;
   constexpr int LAST = S::NPASS - 1;
-  std::vector<double> lds(S::N);
+  std::vector<double> lds(S::N + S::N / 8);
   double x[S::R];
   for (int t = 0; t < S::T; t++) {
     for (int r = 0; r < S::R; r++) x[r] = X[t][r];
-    inv_pass<LOGN, LOGR, LAST>(x, t, itw, q, qinv, mask);
+    inv_pass<LOGN, LOGR, LAST, RED>(x, t, itw, q, qinv);
     for (int r = 0; r < S::R; r++) X[t][r] = x[r];
   }
-  track<LOGR>(X);
+  track(X);
   auto step = [&](auto pass_c) {
     constexpr int P = decltype(pass_c)::value;
     if constexpr (P >= 0 && P < LAST) {
@@ -77,12 +85,13 @@ void inv(std::vector<std::vector<double>> &X, const double *itw, double q, doubl
       }
       for (int t = 0; t < S::T; t++) {
         lds_load<LOGN, LOGR, P>(lds.data(), x, t);
-        inv_pass<LOGN, LOGR, P>(x, t, itw, q, qinv, mask);
+        inv_pass<LOGN, LOGR, P, RED>(x, t, itw, q, qinv);
         for (int r = 0; r < S::R; r++) X[t][r] = x[r];
       }
-      track<LOGR>(X);
+      track(X);
     }
   };
+  step(std::integral_constant<int, 3>{});
   step(std::integral_constant<int, 2>{});
   step(std::integral_constant<int, 1>{});
   step(std::integral_constant<int, 0>{});
@@ -91,15 +100,14 @@ void inv(std::vector<std::vector<double>> &X, const double *itw, double q, doubl
 // c = a * b in Z_q[X]/(X^N + 1): forward transforms of both, b_hat reduced and scaled by
 // N^-1, pointwise product, inverse transform -- the sequence the encryption and decryption
 // kernels use.  a_small: a holds small signed values (as v, s do), else canonical residues.
-template <int LOGN, int LOGR>
+template <int LOGN, int LOGR, int RC>
 int negacyclic(const int64_t *a, const uint64_t *b, uint64_t *c, uint64_t q, uint64_t psi, int a_small) {
   using S = NttShape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
+  if ((double)q > Red::qmax) return -2;
   std::vector<double> twf, twi;
   host::twiddles(q, psi, LOGN, twf, twi);
   const double qd = (double)q, qinv = 1.0 / qd;
-  const uint32_t mf_small = host::forward_reduction_mask(LOGN, qd, 1.0);
-  const uint32_t mf_big = host::forward_reduction_mask(LOGN, qd, qd);
-  const uint32_t mi = host::inverse_reduction_mask(LOGN, qd, 0.75 * qd + 4);
   const double ninv = host::centered(host::inv_mod((uint64_t)S::N % q, q), q);
   std::vector<std::vector<double>> A(S::T, std::vector<double>(S::R)), Bv(S::T, std::vector<double>(S::R));
   for (int t = 0; t < S::T; t++)
@@ -107,36 +115,52 @@ int negacyclic(const int64_t *a, const uint64_t *b, uint64_t *c, uint64_t q, uin
       A[t][r] = (double)a[t + S::T * r];
       Bv[t][r] = (double)b[t + S::T * r];
     }
-  fwd<LOGN, LOGR>(A, twf.data(), qd, qinv, a_small ? mf_small : mf_big);
-  fwd<LOGN, LOGR>(Bv, twf.data(), qd, qinv, mf_big);
+  if (a_small)
+    fwd<LOGN, LOGR, Red::fwd_small>(A, twf.data(), qd, qinv);
+  else
+    fwd<LOGN, LOGR, Red::fwd_big>(A, twf.data(), qd, qinv);
+  fwd<LOGN, LOGR, Red::fwd_big>(Bv, twf.data(), qd, qinv);
   for (int t = 0; t < S::T; t++)
     for (int r = 0; r < S::R; r++) {
       const double bh = reduce(mulmod(Bv[t][r], ninv, qd, qinv), qd, qinv);
       A[t][r] = mulmod(A[t][r], bh, qd, qinv);
     }
-  track<LOGR>(A);
-  inv<LOGN, LOGR>(A, twi.data(), qd, qinv, mi);
+  track(A);
+  inv<LOGN, LOGR, Red::inv>(A, twi.data(), qd, qinv);
   for (int t = 0; t < S::T; t++)
     for (int r = 0; r < S::R; r++) c[t + S::T * r] = (uint64_t)canon(A[t][r], qd, qinv);
   return 0;
+}
+
+template <int LOGN>
+int negacyclic_shape(const int64_t *a, const uint64_t *b, uint64_t *c, uint64_t q, uint64_t psi, int a_small, int logr,
+                     int rc) {
+  if (logr == 4) return rc ? negacyclic<LOGN, 4, 1>(a, b, c, q, psi, a_small) : negacyclic<LOGN, 4, 0>(a, b, c, q, psi, a_small);
+  if (logr == 5) return rc ? negacyclic<LOGN, 5, 1>(a, b, c, q, psi, a_small) : negacyclic<LOGN, 5, 0>(a, b, c, q, psi, a_small);
+  return -1;
 }
 
 }  // namespace
 
 extern "C" {
 
-int emu_negacyclic(const int64_t *a, const uint64_t *b, uint64_t *c, int log_n, uint64_t q, uint64_t psi, int a_small) {
+int emu_negacyclic(const int64_t *a, const uint64_t *b, uint64_t *c, int log_n, uint64_t q, uint64_t psi, int a_small,
+                   int logr, int rc) {
   switch (log_n) {
-    case 11: return negacyclic<11, 5>(a, b, c, q, psi, a_small);
-    case 12: return negacyclic<12, 5>(a, b, c, q, psi, a_small);
-    case 13: return negacyclic<13, 5>(a, b, c, q, psi, a_small);
-    case 14: return negacyclic<14, 5>(a, b, c, q, psi, a_small);
+    case 11: return negacyclic_shape<11>(a, b, c, q, psi, a_small, logr, rc);
+    case 12: return negacyclic_shape<12>(a, b, c, q, psi, a_small, logr, rc);
+    case 13: return negacyclic_shape<13>(a, b, c, q, psi, a_small, logr, rc);
+    case 14: return negacyclic_shape<14>(a, b, c, q, psi, a_small, logr, rc);
     default: return -1;
   }
 }
 
 double emu_max_abs(void) { return g_max_abs; }
-void emu_reset_max(void) { g_max_abs = 0; }
+int emu_lds_bijective(void) { return g_lds_bijective ? 1 : 0; }
+void emu_reset_max(void) {
+  g_max_abs = 0;
+  g_lds_bijective = true;
+}
 
 double emu_mulmod(double a, double w, double q) { return mulmod(a, w, q, 1.0 / q); }
 double emu_reduce(double x, double q) { return reduce(x, q, 1.0 / q); }
@@ -154,6 +178,6 @@ int emu_gauss(uint64_t w, double sigma, int B) {
   std::vector<uint64_t> T = host::cdt_table(sigma, B, kCdtSlots);
   return gauss_of(w, T.data(), B);
 }
-uint32_t emu_fwd_mask(int log_n, double qmax, double in_bound) { return host::forward_reduction_mask(log_n, qmax, in_bound); }
-uint32_t emu_inv_mask(int log_n, double qmax, double in_bound) { return host::inverse_reduction_mask(log_n, qmax, in_bound); }
+uint32_t emu_fwd_mask(int log_n, double qmax, double in_bound) { return forward_schedule(log_n, qmax, in_bound); }
+uint32_t emu_inv_mask(int log_n, double qmax, double in_bound) { return inverse_schedule(log_n, qmax, in_bound); }
 }

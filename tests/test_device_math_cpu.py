@@ -36,9 +36,10 @@ def emu():
         pytest.skip("hipcc not available")
     L = C.CDLL(_build())
     u64p, i64p = C.POINTER(C.c_uint64), C.POINTER(C.c_int64)
-    L.emu_negacyclic.argtypes = [i64p, u64p, u64p, C.c_int, C.c_uint64, C.c_uint64, C.c_int]
+    L.emu_negacyclic.argtypes = [i64p, u64p, u64p, C.c_int, C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_int]
     L.emu_negacyclic.restype = C.c_int
     L.emu_max_abs.restype = C.c_double
+    L.emu_lds_bijective.restype = C.c_int
     for f in ("emu_mulmod",):
         getattr(L, f).argtypes = [C.c_double, C.c_double, C.c_double]
         getattr(L, f).restype = C.c_double
@@ -67,10 +68,12 @@ def _u64(a):
     return np.ascontiguousarray(a, dtype=np.uint64)
 
 
-@pytest.mark.parametrize("log_n,bits", [(11, 30), (12, 36), (13, 50), (14, 50)])
-def test_emulated_ntt_product_matches_oracle(emu, oracle_mod, log_n, bits):
+@pytest.mark.parametrize("log_n,bits,logr", [(11, 30, 5), (12, 36, 5), (12, 36, 4), (13, 50, 5), (13, 50, 4),
+                                            (13, 40, 4), (14, 50, 5), (14, 50, 4), (11, 49, 4)])
+def test_emulated_ntt_product_matches_oracle(emu, oracle_mod, log_n, bits, logr):
     N = 1 << log_n
     rng = np.random.default_rng(log_n * 100 + bits)
+    rc = 0 if bits <= 40 else 1
     for q in oracle_mod.gen_primes(log_n, bits, 2):
         psi = oracle_mod.primitive_2n_root(q, log_n)
         cases = [
@@ -83,21 +86,35 @@ def test_emulated_ntt_product_matches_oracle(emu, oracle_mod, log_n, bits):
         for name, a, b, small in cases:
             emu.emu_reset_max()
             c = np.zeros(N, dtype=np.uint64)
-            rc = emu.emu_negacyclic(a.ctypes.data_as(C.POINTER(C.c_int64)), _u64(b).ctypes.data_as(C.POINTER(C.c_uint64)),
-                                    c.ctypes.data_as(C.POINTER(C.c_uint64)), log_n, q, psi, small)
-            assert rc == 0
+            st = emu.emu_negacyclic(a.ctypes.data_as(C.POINTER(C.c_int64)), _u64(b).ctypes.data_as(C.POINTER(C.c_uint64)),
+                                    c.ctypes.data_as(C.POINTER(C.c_uint64)), log_n, q, psi, small, logr, rc)
+            assert st == 0
             a_res = np.array([int(x) % q for x in a], dtype=np.uint64)
             ref = oracle_mod.negacyclic_mul(a_res, b, q, psi)
             assert np.array_equal(c, ref), (name, q)
             assert emu.emu_max_abs() < 2.0**52, name
+            assert emu.emu_lds_bijective() == 1
 
 
 def test_reduction_schedules(emu):
-    # 36-bit primes never need a reduction inside a transform; 50-bit primes do
+    # 36-bit primes never need a reduction inside a forward transform; 50-bit primes do
     assert emu.emu_fwd_mask(13, 2.0**36, 1.0) == 0
     assert emu.emu_inv_mask(13, 2.0**36, 0.75 * 2**36) == 0
     assert emu.emu_fwd_mask(13, 2.0**50, 2.0**50) != 0
     assert emu.emu_inv_mask(13, 2.0**50, 0.75 * 2**50) != 0
+    # a schedule derived for a larger modulus reduces at least where a smaller one needs to
+    for log_n in (11, 12, 13, 14):
+        for small, big in ((2.0**36, 2.0**40), (2.0**45, 2.0**50)):
+            for f, inb in ((emu.emu_fwd_mask, lambda q: 1.0), (emu.emu_fwd_mask, lambda q: q),
+                           (emu.emu_inv_mask, lambda q: 0.75 * q + 4)):
+                m_small, m_big = f(log_n, small, inb(small)), f(log_n, big, inb(big))
+                # every prefix of stages of the big schedule has at least as many reductions
+                order = range(log_n) if f is emu.emu_fwd_mask else range(log_n - 1, -1, -1)
+                cs = cb = 0
+                for s in order:
+                    cs += (m_small >> s) & 1
+                    cb += (m_big >> s) & 1
+                    assert cb >= cs
 
 
 def test_fp64_modular_arithmetic_exact(emu, oracle_mod):
