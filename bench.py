@@ -30,6 +30,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=192, help="pixels in the oracle's timed sample (0 = skip)")
     ap.add_argument("--phases", default="plain,radix,value,filter,decrypt")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    ap.add_argument("--ntt-width", type=int, default=0, help="values per NTT thread (16 or 32; 0 = library default)")
     return ap.parse_args()
 
 
@@ -117,7 +120,15 @@ def main():
     H, Wd = img.shape
     n = img.size
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.int64, device=dev).fill_(7)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale, device=0)
+    if args.ntt_width:
+        ctx.set_ntt_width(args.ntt_width)
     ctx.keygen(W.keygen_seed(cfg))
     px = torch.from_numpy(img.reshape(-1)).to(dev)
     stream = torch.cuda.Stream(device=dev)

@@ -74,10 +74,11 @@ int resolve_params(const ckks_params *p, host::Resolved *r) {
 
 void free_tables(ckks_ctx *c) {
   DevTables &d = c->dev;
-  void *ptrs[] = {d.tw_fwd, d.tw_inv, d.enc_T, d.cosj, d.cdt, d.s, d.pk, d.pk_hat, d.s_hat};
+  void *ptrs[] = {d.tw_fwd, d.tw_inv, d.enc_T, d.cosj, d.cdt, d.s, d.pk, d.pk_hat, d.s_hat, c->d_lc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevTables{};
+  c->d_lc = nullptr;
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -224,6 +225,8 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   if (e == hipSuccess) e = upload(d.enc_T, host::encode_table(r.log_n, r.log_scale));
   if (e == hipSuccess) e = upload(d.cosj, host::cos_table(r.log_n));
   if (e == hipSuccess) e = upload(d.cdt, host::cdt_table(r.sigma, r.B, kCdtSlots));
+  if (e == hipSuccess) e = dev_alloc(&c->d_lc, 1);
+  if (e == hipSuccess) e = hipMemcpy(c->d_lc, &c->lc, sizeof(LimbConsts), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_tables(c);
     delete c;

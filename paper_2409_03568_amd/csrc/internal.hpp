@@ -62,6 +62,7 @@ struct ckks_ctx {
   int logr = 5;  // 2^logr values per thread in the NTT kernels (4 or 5)
   int rc = 1;    // reduction class of the primes: 0 if all q < 2^40, else 1 (q < 2^50)
   ckks::LimbConsts lc{};
+  ckks::LimbConsts *d_lc = nullptr;  // device copy of lc (kernels read it with scalar loads)
   ckks::DevTables dev{};
   std::vector<uint64_t> ninv;  // N^-1 mod q_i
   bool has_keys = false;

@@ -78,8 +78,9 @@ __global__ void __launch_bounds__(kThreads)
 // written by the plain encryption kernel).
 __global__ void __launch_bounds__(kThreads)
     k_value_gather(const uint64_t *__restrict__ entries, const uint64_t *__restrict__ pool,
-                   const uint32_t *__restrict__ meta, uint64_t rows, int L, int log_n, LimbConsts lc,
-                   uint64_t *__restrict__ out) {
+                   const uint32_t *__restrict__ meta, uint64_t rows, int L, int log_n,
+                   const LimbConsts *__restrict__ lcp, uint64_t *__restrict__ out) {
+  const LimbConsts &lc = *lcp;
   const int N = 1 << log_n;
   const uint64_t S = (uint64_t)2 * L * N;
   for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
@@ -136,7 +137,8 @@ __global__ void __launch_bounds__(kThreads)
 
 __global__ void __launch_bounds__(kThreads)
     k_radix_gather(const uint64_t *__restrict__ entries, const int16_t *__restrict__ meta, uint64_t rows, int L,
-                   int log_n, uint32_t D, LimbConsts lc, uint64_t *__restrict__ out) {
+                   int log_n, uint32_t D, const LimbConsts *__restrict__ lcp, uint64_t *__restrict__ out) {
+  const LimbConsts &lc = *lcp;
   const int N = 1 << log_n;
   const uint64_t S = (uint64_t)2 * L * N;
   for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
@@ -193,7 +195,7 @@ hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const
   const int L = c->prm.L;
   const uint64_t rows = n * 2 * (uint64_t)L;
   hipLaunchKernelGGL(k_value_gather, dim3(grid_for(rows, 1)), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
-                     meta, rows, L, c->prm.log_n, c->lc, out);
+                     meta, rows, L, c->prm.log_n, c->d_lc, out);
   return hipGetLastError();
 }
 
@@ -212,7 +214,7 @@ hipError_t launch_radix_gather(const ckks_ctx *c, const ckks_cache *cache, const
   const int L = c->prm.L;
   const uint64_t rows = n * 2 * (uint64_t)L;
   hipLaunchKernelGGL(k_radix_gather, dim3(grid_for(rows, 1)), dim3(kThreads), 0, st, cache->entries, meta, rows, L,
-                     c->prm.log_n, cache->digits, c->lc, out);
+                     c->prm.log_n, cache->digits, c->d_lc, out);
   return hipGetLastError();
 }
 

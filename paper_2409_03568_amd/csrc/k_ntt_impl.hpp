@@ -17,7 +17,8 @@ struct Shape : NttShape<LOGN, LOGR> {
   static constexpr int LAST = NttShape<LOGN, LOGR>::NPASS - 1;
   // dynamic LDS: the exchange space (N doubles with padding, see lds_pos), the Gaussian
   // table, and a reduction area
-  static constexpr size_t lds_bytes = sizeof(double) * ((size_t)(1 << LOGN) * 9 / 8 + kCdtSlots + 64);
+  static constexpr int SLOTS = LdsSlots<LOGN, LOGR>::value;
+  static constexpr size_t lds_bytes = sizeof(double) * ((size_t)SLOTS + kCdtSlots + 64);
 };
 
 // Draw the packed samples of one polynomial triple into LDS and read them back in
@@ -60,12 +61,14 @@ __device__ __forceinline__ int smp_g(uint32_t s, int shift, int B) { return (int
 //   x = NTT(v); c0 = INTT(x * pk0^) + e0 + m; c1 = INTT(x * pk1^) + e1
 // ---------------------------------------------------------------------------
 template <int LOGN, int LOGR, int RC>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_encrypt(EncJob job, LimbConsts lc, DevTables dt) {
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_encrypt(EncJob job, const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
   using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
+  const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
-  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N + N / 8);
+  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
   uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
@@ -110,12 +113,14 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_encrypt(EncJob job, Limb
 // key generation, one workgroup per limb l: pk0_l = -a_l * s + e, pk1_l = a_l
 // ---------------------------------------------------------------------------
 template <int LOGN, int LOGR, int RC>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keygen(uint64_t k0, uint64_t k1, LimbConsts lc, DevTables dt) {
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_keygen(uint64_t k0, uint64_t k1, const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
   using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
+  const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
-  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + N + N / 8);
+  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
   uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
@@ -178,10 +183,12 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keygen(uint64_t k0, uint
 //   blockIdx.y = 0: s_hat_l * N^-1;  1: pk0_hat_l * N^-1;  2: pk1_hat_l * N^-1
 // ---------------------------------------------------------------------------
 template <int LOGN, int LOGR, int RC>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keys_prepare(LimbConsts lc, DevTables dt) {
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_keys_prepare(const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
   using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
+  const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
   const int tid = threadIdx.x, l = blockIdx.x, which = blockIdx.y, L = lc.L;
   const double q = lc.q[l], qinv = lc.qinv[l];
@@ -209,12 +216,13 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR)) k_keys_prepare(LimbConsts 
 template <int LOGN, int LOGR, int RC>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     k_decrypt(const uint64_t *__restrict__ cts, uint64_t n, int level, double inv_scale, double *__restrict__ out,
-              LimbConsts lc, DevTables dt) {
+              const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
   using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
+  const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
-  double *red = lds + N + N / 8 + kCdtSlots;
+  double *red = lds + S::SLOTS + kCdtSlots;
   const int tid = threadIdx.x;
   const double q = lc.q[0], qinv = lc.qinv[0];
   for (uint64_t i = blockIdx.x; i < n; i += gridDim.x) {
@@ -263,20 +271,20 @@ struct Launch {
   static hipError_t encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
     hipError_t e = set_lds<LOGN, LOGR>(k_encrypt<LOGN, LOGR, RC>);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_encrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, job, c->lc,
+    hipLaunchKernelGGL((k_encrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, job, c->d_lc,
                        c->dev);
     return hipGetLastError();
   }
   static hipError_t keygen(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
     hipError_t e = set_lds<LOGN, LOGR>(k_keygen<LOGN, LOGR, RC>);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_keygen<LOGN, LOGR, RC>), dim3(c->lc.L), dim3(S::T), S::lds_bytes, st, s0, s1, c->lc, c->dev);
+    hipLaunchKernelGGL((k_keygen<LOGN, LOGR, RC>), dim3(c->lc.L), dim3(S::T), S::lds_bytes, st, s0, s1, c->d_lc, c->dev);
     return hipGetLastError();
   }
   static hipError_t prepare(const ckks_ctx *c, hipStream_t st) {
     hipError_t e = set_lds<LOGN, LOGR>(k_keys_prepare<LOGN, LOGR, RC>);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_keys_prepare<LOGN, LOGR, RC>), dim3(c->lc.L, 3), dim3(S::T), S::lds_bytes, st, c->lc, c->dev);
+    hipLaunchKernelGGL((k_keys_prepare<LOGN, LOGR, RC>), dim3(c->lc.L, 3), dim3(S::T), S::lds_bytes, st, c->d_lc, c->dev);
     return hipGetLastError();
   }
   static hipError_t decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
@@ -285,7 +293,7 @@ struct Launch {
     if (e != hipSuccess) return e;
     const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
     hipLaunchKernelGGL((k_decrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, cts, n, level,
-                       1.0 / scale, out, c->lc, c->dev);
+                       1.0 / scale, out, c->d_lc, c->dev);
     return hipGetLastError();
   }
 };

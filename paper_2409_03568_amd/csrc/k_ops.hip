@@ -61,7 +61,9 @@ __global__ void __launch_bounds__(kRowThreads)
 // Rows are the c0 rows only: row r is ciphertext r / level, limb r % level.
 __global__ void __launch_bounds__(kRowThreads)
     k_add_const(uint64_t *__restrict__ a, uint64_t rows, int level, int log_n, double scale,
-                const double *__restrict__ d_b, double b, const double *__restrict__ cosj, LimbConsts lc) {
+                const double *__restrict__ d_b, double b, const double *__restrict__ cosj,
+                const LimbConsts *__restrict__ lcp) {
+  const LimbConsts &lc = *lcp;
   const int N = 1 << log_n;
   for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
     const uint64_t ct = row / (uint64_t)level;
@@ -235,7 +237,7 @@ hipError_t launch_add_const(const ckks_ctx *c, uint64_t *a, uint64_t n, int leve
                             double b, hipStream_t st) {
   const uint64_t rows = n * (uint64_t)level;
   hipLaunchKernelGGL(k_add_const, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, rows, level, c->prm.log_n, scale,
-                     d_b, b, c->dev.cosj, c->lc);
+                     d_b, b, c->dev.cosj, c->d_lc);
   return hipGetLastError();
 }
 

@@ -92,30 +92,36 @@ struct Schedule {
 // layouts
 // ---------------------------------------------------------------------------
 // Element index held in register r by thread tid during pass PASS.
+// (Indices are unsigned 32-bit so that loads can address a uniform base plus a 32-bit
+// per-lane offset instead of building a 64-bit address per load.)
 template <int LOGN, int LOGR, int PASS>
-CKKS_HD int elem_index(int tid, int r) {
+CKKS_HD unsigned elem_index(unsigned tid, unsigned r) {
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS);
   constexpr int LTLO = LOGN - S0 - P;  // log2 of the smallest butterfly distance in the pass
-  const int u = r >> P, k = r & ((1 << P) - 1);
-  const int g = tid + S::T * u;
-  const int blk = g >> LTLO, off = g & ((1 << LTLO) - 1);
+  const unsigned u = r >> P, k = r & ((1u << P) - 1);
+  const unsigned g = tid + (unsigned)S::T * u;
+  const unsigned blk = g >> LTLO, off = g & ((1u << LTLO) - 1);
   return (blk << (LOGN - S0)) + (k << LTLO) + off;
 }
 
-// LDS position of element e: one padding slot after every 8 elements (N + N/8 slots).
-// The last pass's lanes are 8 elements apart and would otherwise hit the same banks; with
-// the padding they are 9 apart.  Every pass's positions stay affine in the register index
-// (the padding depends only on bits that the register index does not change), so the LDS
-// accesses of one thread share a base address with immediate offsets.
-CKKS_HD int lds_pos(int e) { return e + (e >> 3); }
+// LDS position of element e: one padding slot after every 2^(LOGR-1) elements.  In each
+// pass the 16 lanes of a quarter-wave then fall on 16 different 8-byte banks (lanes one
+// apart, in pairs 2^(LOGN-S0) apart, or 2^(P) apart in the last pass, which the padding
+// turns into an odd stride); for 16 values per thread every pass is conflict-free, for 32
+// the middle pass keeps a two-way conflict.  The padding depends almost only on bits the
+// register index does not change, so one thread's accesses mostly share a base address
+// with immediate offsets.
+template <int LOGR>
+CKKS_HD unsigned lds_pos(unsigned e) { return e + (e >> (LOGR - 1)); }
+template <int LOGN, int LOGR>
+struct LdsSlots {
+  static constexpr int value = (1 << LOGN) + ((1 << LOGN) >> (LOGR - 1));
+};
 
 // ---------------------------------------------------------------------------
 // passes
 // ---------------------------------------------------------------------------
-// Keeps the device scheduler from interleaving consecutive stages: a pass compiles to
-// one straight-line block, and hoisting later stages' loads and arithmetic over earlier
-// ones raises register pressure past what two waves per SIMD can hold.
 // The thread index as a value the compiler cannot prove loop-invariant: address
 // arithmetic derived from it stays next to its use instead of being hoisted out of the
 // per-ciphertext loops, where dozens of precomputed pointers would stay live.
@@ -126,6 +132,9 @@ CKKS_HD int opaque(int v) {
   return v;
 }
 
+// Keeps the device scheduler from interleaving consecutive stages: a pass compiles to
+// one straight-line block, and hoisting later stages' loads and arithmetic over earlier
+// ones raises register pressure past what two waves per SIMD can hold.
 CKKS_HD void stage_fence() {
 #if defined(__HIP_DEVICE_COMPILE__)
   __builtin_amdgcn_sched_barrier(0);
@@ -141,8 +150,8 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
   constexpr int LTLO = LOGN - S0 - P;
 #pragma unroll
   for (int u = 0; u < G; u++) {
-    const int g = tid + S::T * u;
-    const int blk = g >> LTLO;
+    const unsigned g = (unsigned)tid + (unsigned)S::T * u;
+    const unsigned blk = g >> LTLO;
 #pragma unroll
     for (int l = 0; l < P; l++) {
       const int s = S0 + l;
@@ -150,7 +159,7 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 #pragma unroll
       for (int k = 0; k < (1 << P); k++) {
         if (k & half) continue;
-        const double W = tw[(1 << s) + (blk << l) + (k >> (P - l))];
+        const double W = tw[(1u << s) + (blk << l) + (unsigned)(k >> (P - l))];
         ct_butterfly(x[u * (1 << P) + k], x[u * (1 << P) + k + half], W, q, qinv);
       }
       if ((RED >> s) & 1u) {
@@ -172,8 +181,8 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
   constexpr int LTLO = LOGN - S0 - P;
 #pragma unroll
   for (int u = 0; u < G; u++) {
-    const int g = tid + S::T * u;
-    const int blk = g >> LTLO;
+    const unsigned g = (unsigned)tid + (unsigned)S::T * u;
+    const unsigned blk = g >> LTLO;
 #pragma unroll
     for (int l = P - 1; l >= 0; l--) {
       const int s = S0 + l;
@@ -181,7 +190,7 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 #pragma unroll
       for (int k = 0; k < (1 << P); k++) {
         if (k & half) continue;
-        const double W = itw[(1 << s) + (blk << l) + (k >> (P - l))];
+        const double W = itw[(1u << s) + (blk << l) + (unsigned)(k >> (P - l))];
         double &X = x[u * (1 << P) + k];
         double &Y = x[u * (1 << P) + k + half];
         gs_butterfly(X, Y, W, q, qinv);
@@ -196,14 +205,14 @@ template <int LOGN, int LOGR, int PASS>
 CKKS_HD void lds_store(double *lds, const double (&x)[1 << LOGR], int tid_in) {
   const int tid = opaque(tid_in);
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) lds[lds_pos(elem_index<LOGN, LOGR, PASS>(tid, r))] = x[r];
+  for (int r = 0; r < (1 << LOGR); r++) lds[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(tid, r))] = x[r];
 }
 
 template <int LOGN, int LOGR, int PASS>
 CKKS_HD void lds_load(const double *lds, double (&x)[1 << LOGR], int tid_in) {
   const int tid = opaque(tid_in);
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) x[r] = lds[lds_pos(elem_index<LOGN, LOGR, PASS>(tid, r))];
+  for (int r = 0; r < (1 << LOGR); r++) x[r] = lds[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(tid, r))];
 }
 
 // Passes 1..NPASS-1 of the forward transform (pass 0 is run by the caller on the

@@ -30,7 +30,7 @@ void track(const std::vector<std::vector<double>> &X) {
 template <int LOGN, int LOGR, uint32_t RED>
 void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double qinv) {
   using S = NttShape<LOGN, LOGR>;
-  std::vector<double> lds(S::N + S::N / 8);
+  std::vector<double> lds(LdsSlots<LOGN, LOGR>::value);
   double x[S::R];
   for (int t = 0; t < S::T; t++) {
     for (int r = 0; r < S::R; r++) x[r] = X[t][r];
@@ -41,11 +41,11 @@ void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double
   auto step = [&](auto pass_c) {
     constexpr int P = decltype(pass_c)::value;
     if constexpr (P >= 1 && P < S::NPASS) {
-      std::vector<int> hit(S::N + S::N / 8, 0);
+      std::vector<int> hit(LdsSlots<LOGN, LOGR>::value, 0);
       for (int t = 0; t < S::T; t++) {
         for (int r = 0; r < S::R; r++) {
           x[r] = X[t][r];
-          hit[lds_pos(elem_index<LOGN, LOGR, P - 1>(t, r))]++;
+          hit[lds_pos<LOGR>(elem_index<LOGN, LOGR, P - 1>(t, r))]++;
         }
         lds_store<LOGN, LOGR, P - 1>(lds.data(), x, t);
       }
@@ -68,7 +68,7 @@ template <int LOGN, int LOGR, uint32_t RED>
 void inv(std::vector<std::vector<double>> &X, const double *itw, double q, double qinv) {
   using S = NttShape<LOGN, LOGR>;
   constexpr int LAST = S::NPASS - 1;
-  std::vector<double> lds(S::N + S::N / 8);
+  std::vector<double> lds(LdsSlots<LOGN, LOGR>::value);
   double x[S::R];
   for (int t = 0; t < S::T; t++) {
     for (int r = 0; r < S::R; r++) x[r] = X[t][r];
