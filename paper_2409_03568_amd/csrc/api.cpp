@@ -531,16 +531,19 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
     HIP_TRY(hipFreeAsync(bad, st), "flag free");
     return CKKS_OK;
   }
-  uint32_t *meta = nullptr, *miss = nullptr, *nmiss = nullptr;
+  uint32_t *meta = nullptr, *miss = nullptr, *hits = nullptr, *counters = nullptr;
   HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&meta), n * sizeof(uint32_t), st), "meta alloc");
   HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&miss), n * sizeof(uint32_t), st), "miss list alloc");
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&nmiss), sizeof(uint32_t), st), "miss count alloc");
-  HIP_TRY(launch_value_meta(ctx, cache, d_px, n, first_index, seed[0], seed[1], meta, miss, nmiss, st), "value meta");
-  HIP_TRY(launch_value_gather(ctx, cache, meta, n, out->data, st), "value gather");
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&hits), n * sizeof(uint32_t), st), "hit list alloc");
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&counters), (2 + (size_t)cache->pool) * sizeof(uint32_t), st),
+          "counter alloc");
+  HIP_TRY(launch_value_meta(ctx, cache, d_px, n, first_index, seed[0], seed[1], meta, miss, counters, hits, st),
+          "value meta");
+  HIP_TRY(launch_value_gather(ctx, cache, meta, counters, hits, n, out->data, st), "value gather");
   EncJob job;
   job.px = d_px;
   job.list = miss;
-  job.list_count = nmiss;
+  job.list_count = counters;
   job.n = n;
   job.first_index = first_index;
   job.seed0 = seed[0];
@@ -549,7 +552,8 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
   HIP_TRY(launch_encrypt(ctx, job, std::min<uint64_t>(n, kListGrid), st), "miss encryption");
   HIP_TRY(hipFreeAsync(meta, st), "meta free");
   HIP_TRY(hipFreeAsync(miss, st), "miss list free");
-  HIP_TRY(hipFreeAsync(nmiss, st), "miss count free");
+  HIP_TRY(hipFreeAsync(hits, st), "hit list free");
+  HIP_TRY(hipFreeAsync(counters, st), "counter free");
   return CKKS_OK;
 }
 

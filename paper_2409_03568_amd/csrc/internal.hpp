@@ -14,7 +14,7 @@ namespace ckks {
 constexpr int kMaxL = 16;
 constexpr int kMaxDigits = 8;
 
-// Per-limb constants passed by value to every kernel.
+// Per-limb constants; kernels read the device copy held by the context.
 struct LimbConsts {
   int L;                 // limbs of the context
   int B;                 // Gaussian bound (0 = no noise)
@@ -104,11 +104,14 @@ hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *o
 
 hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t n, uint32_t topk, uint32_t *hist,
                                  ckks_cache *cache, hipStream_t stream);
+// Value-cache metadata for n pixels: meta[t], the miss list, and the hit list grouped by
+// pool member.  counters = [miss count, hit count, per-member counts (pool entries)].
 hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t first_index, uint64_t seed0, uint64_t seed1, uint32_t *meta,
-                             uint32_t *miss_list, uint32_t *miss_count, hipStream_t stream);
-hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta, uint64_t n,
-                               uint64_t *out, hipStream_t stream);
+                             uint32_t *miss_list, uint32_t *counters, uint32_t *hits, hipStream_t stream);
+hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta,
+                               const uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
+                               hipStream_t stream);
 hipError_t launch_radix_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t first_index, uint64_t seed0, uint64_t seed1, int16_t *meta, uint32_t *bad,
                              hipStream_t stream);
@@ -117,5 +120,20 @@ hipError_t launch_radix_gather(const ckks_ctx *c, const ckks_cache *cache, const
 
 // Largest grid the persistent (list-driven) encryption uses.
 constexpr uint64_t kListGrid = 8192;
+
+// The dispatcher hands workgroup b to XCD b mod 8.  This maps the hardware index to a
+// logical one so that each XCD receives a contiguous range of logical workgroups (a
+// bijection on [0, nb) for any nb): neighbouring logical workgroups, which read
+// neighbouring data, then share one XCD's L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_logical_block(uint32_t b, uint32_t nb) {
+  const uint32_t x = b % kXcds, i = b / kXcds;
+  const uint32_t per = nb / kXcds, rem = nb % kXcds;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+// 16-byte vector of two residues, for non-temporal stores of ciphertext rows that are not
+// read again by the same kernel (they would otherwise evict cache tables from L2/MALL).
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 }  // namespace ckks

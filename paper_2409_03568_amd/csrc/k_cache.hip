@@ -56,17 +56,18 @@ __global__ void __launch_bounds__(256)
 
 // Per pixel t: meta = (slot + 1) | u << 16 for a cached value, with pool member
 // u = floor(npool * w / 2^64) from auxiliary word 0; 0 for a value that is not cached,
-// whose index is appended to the miss list.
+// whose index is appended to the miss list.  Hits are counted per pool member.
 __global__ void __launch_bounds__(kThreads)
     k_value_meta(const uint8_t *__restrict__ px, uint64_t n, uint64_t first_index, uint64_t s0, uint64_t s1,
                  const int16_t *__restrict__ slot_of, uint32_t npool, uint32_t *__restrict__ meta,
-                 uint32_t *__restrict__ miss_list, uint32_t *miss_count) {
+                 uint32_t *__restrict__ miss_list, uint32_t *miss_count, uint32_t *__restrict__ ucount) {
   for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
     const int slot = slot_of[px[t]];
     if (slot >= 0) {
       const uint64_t w = philox4x64_10(first_index + t, kTagAux, 0, 0, s0, s1).w[0];
       const uint32_t u = (uint32_t)mulhi64(w, npool);
       meta[t] = (uint32_t)(slot + 1) | (u << 16);
+      atomicAdd(&ucount[u], 1u);
     } else {
       meta[t] = 0;
       miss_list[atomicAdd(miss_count, 1u)] = (uint32_t)t;
@@ -74,30 +75,79 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// out row = entry[slot] row + pool[u] row for cached pixels (rows of missed pixels are
-// written by the plain encryption kernel).
+// Exclusive prefix sum of the per-member hit counts (in place: they become the bucket
+// cursors) and the total hit count.  One workgroup of kScanThreads threads.
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads) k_bucket_scan(uint32_t *__restrict__ ucount, uint32_t npool,
+                                                              uint32_t *__restrict__ total) {
+  __shared__ uint32_t part[kScanThreads];
+  const uint32_t per = (npool + kScanThreads - 1) / kScanThreads;
+  const uint32_t lo = threadIdx.x * per, hi = min(lo + per, npool);
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; i++) s += ucount[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t v = threadIdx.x >= (uint32_t)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;  // exclusive prefix of this thread's range
+  for (uint32_t i = lo; i < hi; i++) {
+    const uint32_t c = ucount[i];
+    ucount[i] = run;
+    run += c;
+  }
+  if (threadIdx.x == kScanThreads - 1) *total = part[kScanThreads - 1];
+}
+
+// Hit pixels grouped by pool member (order inside a group is arbitrary; every output row
+// is written independently, so the result does not depend on it).
+__global__ void __launch_bounds__(kThreads)
+    k_value_scatter(const uint32_t *__restrict__ meta, uint64_t n, uint32_t *__restrict__ cursor,
+                    uint32_t *__restrict__ hits) {
+  for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t m = meta[t];
+    if (m != 0) hits[atomicAdd(&cursor[m >> 16], 1u)] = (uint32_t)t;
+  }
+}
+
+// out = entry[slot] + pool[u] for cached pixels (missed pixels are written by the plain
+// encryption kernel).  One workgroup per hit-list position (XCD-contiguous logical
+// order), streaming all 2L rows of that ciphertext: the hit list is grouped by pool
+// member, so each XCD works through a few pool entries at a time and they stay in its
+// L2, while the output streams past with non-temporal stores.
 __global__ void __launch_bounds__(kThreads)
     k_value_gather(const uint64_t *__restrict__ entries, const uint64_t *__restrict__ pool,
-                   const uint32_t *__restrict__ meta, uint64_t rows, int L, int log_n,
-                   const LimbConsts *__restrict__ lcp, uint64_t *__restrict__ out) {
+                   const uint32_t *__restrict__ meta, const uint32_t *__restrict__ hits,
+                   const uint32_t *__restrict__ hit_count, int L, int log_n, const LimbConsts *__restrict__ lcp,
+                   uint64_t *__restrict__ out) {
   const LimbConsts &lc = *lcp;
   const int N = 1 << log_n;
   const uint64_t S = (uint64_t)2 * L * N;
-  for (uint64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-    const uint64_t ct = row / (uint64_t)(2 * L);
-    const int pl = (int)(row % (uint64_t)(2 * L));
+  const uint64_t nh = *hit_count;
+  const uint64_t nb = gridDim.x;
+  for (uint64_t idx = xcd_logical_block(blockIdx.x, gridDim.x); idx < nh; idx += nb) {
+    const uint64_t ct = hits[idx];
     const uint32_t m = meta[ct];
-    if (m == 0) continue;
-    const uint64_t q = lc.qi[pl % L];
-    const ulonglong2 *pe = reinterpret_cast<const ulonglong2 *>(entries + (uint64_t)((m & 0xffffu) - 1) * S + (uint64_t)pl * N);
-    const ulonglong2 *pz = reinterpret_cast<const ulonglong2 *>(pool + (uint64_t)(m >> 16) * S + (uint64_t)pl * N);
-    ulonglong2 *po = reinterpret_cast<ulonglong2 *>(out + row * N);
-    for (int i = threadIdx.x; i < N / 2; i += kThreads) {
-      const ulonglong2 a = pe[i], b = pz[i];
-      ulonglong2 z;
-      z.x = add_mod(a.x, b.x, q);
-      z.y = add_mod(a.y, b.y, q);
-      po[i] = z;
+    const u64x2 *pe = reinterpret_cast<const u64x2 *>(entries + (uint64_t)((m & 0xffffu) - 1) * S);
+    const u64x2 *pz = reinterpret_cast<const u64x2 *>(pool + (uint64_t)(m >> 16) * S);
+    u64x2 *po = reinterpret_cast<u64x2 *>(out + ct * S);
+    for (int pl = 0; pl < 2 * L; pl++) {
+      const uint64_t q = lc.qi[pl % L];
+      const int base = pl * (N / 2);
+      for (int i = threadIdx.x; i < N / 2; i += 2 * kThreads) {
+        const u64x2 a0 = pe[base + i], b0 = pz[base + i];
+        const u64x2 a1 = pe[base + i + kThreads], b1 = pz[base + i + kThreads];
+        u64x2 z0, z1;
+        z0.x = add_mod(a0.x, b0.x, q);
+        z0.y = add_mod(a0.y, b0.y, q);
+        z1.x = add_mod(a1.x, b1.x, q);
+        z1.y = add_mod(a1.y, b1.y, q);
+        __builtin_nontemporal_store(z0, po + base + i);
+        __builtin_nontemporal_store(z1, po + base + i + kThreads);
+      }
     }
   }
 }
@@ -135,6 +185,11 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// out row = entry0 row + sum_i k_i entry(1+i) row, in exact FP64 arithmetic: each
+// product k_i e is a modular product with a small multiplier (|k_i| <= 256), the sum of
+// at most 1 + 8 reduced terms stays below 2^53, and one final reduction makes it
+// canonical.  The D + 1 table rows (D + 1 rows of N residues per limb and polynomial)
+// stay L2-resident; the output is written with non-temporal stores.
 __global__ void __launch_bounds__(kThreads)
     k_radix_gather(const uint64_t *__restrict__ entries, const int16_t *__restrict__ meta, uint64_t rows, int L,
                    int log_n, uint32_t D, const LimbConsts *__restrict__ lcp, uint64_t *__restrict__ out) {
@@ -145,19 +200,27 @@ __global__ void __launch_bounds__(kThreads)
     const uint64_t ct = row / (uint64_t)(2 * L);
     const int pl = (int)(row % (uint64_t)(2 * L));
     const int l = pl % L;
-    const uint64_t q = lc.qi[l];
-    const double qinv = lc.qinv[l];
-    int k[kMaxDigits];
+    const double q = lc.q[l], qinv = lc.qinv[l];
+    double k[kMaxDigits];
 #pragma unroll
-    for (int i = 0; i < kMaxDigits; i++) k[i] = meta[ct * kMaxDigits + i];
-    const uint64_t *e0 = entries + (uint64_t)pl * N;
-    uint64_t *po = out + row * N;
-    for (int j = threadIdx.x; j < N; j += kThreads) {
-      int64_t acc = (int64_t)e0[j];
+    for (int i = 0; i < kMaxDigits; i++) k[i] = (double)meta[ct * kMaxDigits + i];
+    const u64x2 *e0 = reinterpret_cast<const u64x2 *>(entries + (uint64_t)pl * N);
+    u64x2 *po = reinterpret_cast<u64x2 *>(out + row * N);
+    for (int j = threadIdx.x; j < N / 2; j += kThreads) {
+      const u64x2 a = e0[j];
+      double x0 = u64_to_f64(a.x), x1 = u64_to_f64(a.y);
 #pragma unroll
-      for (int i = 0; i < kMaxDigits; i++)
-        if ((uint32_t)i < D) acc += (int64_t)k[i] * (int64_t)e0[(uint64_t)(1 + i) * S + j];
-      po[j] = mod_i64(acc, q, qinv);
+      for (int i = 0; i < kMaxDigits; i++) {
+        if ((uint32_t)i < D) {
+          const u64x2 b = e0[(uint64_t)(1 + i) * (S / 2) + j];
+          x0 += mulmod(u64_to_f64(b.x), k[i], q, qinv);
+          x1 += mulmod(u64_to_f64(b.y), k[i], q, qinv);
+        }
+      }
+      u64x2 z;
+      z.x = f64_to_u64(canon(x0, q, qinv));
+      z.y = f64_to_u64(canon(x1, q, qinv));
+      __builtin_nontemporal_store(z, po + j);
     }
   }
 }
@@ -182,20 +245,24 @@ hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t 
 
 hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t first_index, uint64_t seed0, uint64_t seed1, uint32_t *meta,
-                             uint32_t *miss_list, uint32_t *miss_count, hipStream_t st) {
+                             uint32_t *miss_list, uint32_t *counters, uint32_t *hits, hipStream_t st) {
   (void)c;
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, miss_count, 1u, 0u);
+  uint32_t *miss_count = counters, *hit_count = counters + 1, *ucount = counters + 2;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 + cache->pool, kThreads)), dim3(kThreads), 0, st, counters,
+                     2u + cache->pool, 0u);
   hipLaunchKernelGGL(k_value_meta, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, px, n, first_index, seed0,
-                     seed1, cache->slot_of, cache->pool, meta, miss_list, miss_count);
+                     seed1, cache->slot_of, cache->pool, meta, miss_list, miss_count, ucount);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanThreads), 0, st, ucount, cache->pool, hit_count);
+  hipLaunchKernelGGL(k_value_scatter, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, meta, n, ucount, hits);
   return hipGetLastError();
 }
 
-hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta, uint64_t n,
-                               uint64_t *out, hipStream_t st) {
-  const int L = c->prm.L;
-  const uint64_t rows = n * 2 * (uint64_t)L;
-  hipLaunchKernelGGL(k_value_gather, dim3(grid_for(rows, 1)), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
-                     meta, rows, L, c->prm.log_n, c->d_lc, out);
+hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta,
+                               const uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
+                               hipStream_t st) {
+  // n is an upper bound of the hit count, which the kernel reads
+  hipLaunchKernelGGL(k_value_gather, dim3(grid_for(n, 1)), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
+                     meta, hits, counters + 1, c->prm.L, c->prm.log_n, c->d_lc, out);
   return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
           const int j = tid + T * r;
           double v = y[r] + (double)smp_g(smp[r], poly == 0 ? 8 : 16, B);
           if (poly == 0) v += __builtin_rint(value * dt.enc_T[j]);
-          dst[j] = (uint64_t)canon(v, q, qinv);
+          __builtin_nontemporal_store((uint64_t)canon(v, q, qinv), dst + j);
         }
       }
     }
@@ -213,8 +213,11 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 // decryption of limb 0 and decoding of slot 0:
 //   d = c0 + INTT(NTT(c1) * s_hat); out = sum_j center(d_j) cos(pi j/N) / scale
 // ---------------------------------------------------------------------------
+// Register budget: enough for two workgroups per CU (the LDS of two fits for N <= 8192),
+// so one workgroup's waves compute while the other's wait at a barrier.
 template <int LOGN, int LOGR, int RC>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    __attribute__((amdgpu_waves_per_eu((1 << (LOGN - LOGR)) >= 256 ? (1 << (LOGN - LOGR)) / 128 : 1)))
     k_decrypt(const uint64_t *__restrict__ cts, uint64_t n, int level, double inv_scale, double *__restrict__ out,
               const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;

@@ -113,88 +113,117 @@ __global__ void __launch_bounds__(kRowThreads)
 }
 
 // Fused k x k mean filter with clamped borders: out(y,x) = rescale(K * sum of the window).
-// Thread (x, poly, j) walks down the image keeping the horizontal window sums of the
-// last k rows in a ring, so every input residue is loaded k times (from L2) and read
-// from HBM once; the vertical sum is updated by adding the new row and subtracting the
-// row that leaves (exact modular arithmetic, so the order does not matter).
+// Thread (x-tile, poly, j) owns XT adjacent output columns of coefficient j and walks down
+// the image, keeping the horizontal window sums of the last k rows in a ring; the
+// vertical sum is updated by adding the row that enters and subtracting the row that
+// leaves.  Arithmetic is exact FP64 on signed representatives:
+//   a horizontal sum of k <= 7 canonical residues is below 7q < 2^53 and is reduced to
+//   |h| <= q/2 + 2; the vertical sum of k such values stays below 3.5q + 14 < 2^52; the
+//   product with the centered multiplier K (|K| <= q/2) has |v K / q| < 1.75q < 2^51, so
+//   mulmod applies and returns |m| < 0.94q; the rescale numerator m_i + h - r stays below
+//   2.5 * 2^50 and its product with the centered q_last^-1 is canonicalised at the end.
+// Since every step is exact modular arithmetic the result equals the sum, multiplication
+// and rescale applied one after another.
 struct FilterConsts {
-  uint64_t q[kMaxL];
-  uint64_t K[kMaxL], Kp[kMaxL];          // multiplier K = rint(q_last / k^2) mod q_i
-  uint64_t h_mod[kMaxL];                 // floor(q_last/2) mod q_i
-  uint64_t qlinv[kMaxL], qlinv_p[kMaxL];  // q_last^-1 mod q_i
-  uint64_t qlast, h;
+  double q[kMaxL], qinv[kMaxL];
+  double K[kMaxL];      // K = rint(q_last / k^2) mod q_i, centered
+  double qlinv[kMaxL];  // q_last^-1 mod q_i, centered
+  double h;             // floor(q_last / 2)
 };
 
-template <int KW, int LV>
+constexpr int kFilterWaves = kRowThreads / 64;
+
+template <int KW, int LV, int XT>
 __global__ void __launch_bounds__(kRowThreads)
     k_mean_filter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t H, uint32_t W, int log_n,
-                  FilterConsts fc) {
-  constexpr int RAD = KW / 2;
+                  uint32_t groups, FilterConsts fc) {
+  constexpr int RAD = KW / 2, XC = XT + 2 * RAD;
   const int N = 1 << log_n;
-  const uint64_t gid = (uint64_t)blockIdx.x * kRowThreads + threadIdx.x;
-  const int j = (int)(gid & (uint64_t)(N - 1));
-  const uint64_t rest = gid >> log_n;
+  // logical workgroup lb = (64-coefficient chunk jc, poly, tile group g), g fastest; its
+  // wave w takes column tile kFilterWaves * g + w.  The tile groups of one (jc, poly) run
+  // side by side on one XCD and walk down the rows at about the same pace, so a halo
+  // column read by two neighbouring tiles is mostly served by that XCD's L2.
+  const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const uint32_t g = lb % groups;
+  const uint32_t rest = lb / groups;
   const int poly = (int)(rest & 1);
-  const uint64_t x = rest >> 1;
-  if (x >= W) return;
-  uint32_t xs[KW];
+  const int j = (int)((rest >> 1) * 64 + (threadIdx.x & 63));
+  const uint64_t x0 = ((uint64_t)g * kFilterWaves + (threadIdx.x >> 6)) * XT;
+  if (x0 >= W) return;
+  uint32_t xs[XC];
 #pragma unroll
-  for (int d = 0; d < KW; d++) {
-    const int64_t xx = (int64_t)x + d - RAD;
+  for (int d = 0; d < XC; d++) {
+    const int64_t xx = (int64_t)x0 + d - RAD;
     xs[d] = (uint32_t)(xx < 0 ? 0 : (xx >= (int64_t)W ? W - 1 : xx));
   }
   const uint64_t ct_stride = (uint64_t)2 * LV * N;
   const uint64_t base = (uint64_t)poly * LV * N + j;
-  auto hsum = [&](int64_t yy, uint64_t (&h)[LV]) {
+  // horizontal sums of input row yy for the XT output columns
+  auto hsum = [&](int64_t yy, double (&h)[XT][LV]) {
     const uint64_t y = (uint64_t)(yy < 0 ? 0 : (yy >= (int64_t)H ? H - 1 : yy));
+    double c[XC][LV];
 #pragma unroll
-    for (int i = 0; i < LV; i++) h[i] = 0;
-#pragma unroll
-    for (int d = 0; d < KW; d++) {
+    for (int d = 0; d < XC; d++) {
       const uint64_t *p = in + (y * W + xs[d]) * ct_stride + base;
 #pragma unroll
-      for (int i = 0; i < LV; i++) h[i] = add_mod(h[i], p[(size_t)i * N], fc.q[i]);
+      for (int i = 0; i < LV; i++) c[d][i] = u64_to_f64(p[(size_t)i * N]);
+    }
+#pragma unroll
+    for (int t = 0; t < XT; t++) {
+#pragma unroll
+      for (int i = 0; i < LV; i++) {
+        double s = c[t][i];
+#pragma unroll
+        for (int d = 1; d < KW; d++) s += c[t + d][i];
+        h[t][i] = reduce(s, fc.q[i], fc.qinv[i]);
+      }
     }
   };
-  uint64_t ring[KW][LV];
-  uint64_t v[LV];
+  double ring[KW][XT][LV];
+  double v[XT][LV];
 #pragma unroll
-  for (int i = 0; i < LV; i++) v[i] = 0;
+  for (int t = 0; t < XT; t++)
+#pragma unroll
+    for (int i = 0; i < LV; i++) v[t][i] = 0.0;
 #pragma unroll
   for (int d = 0; d < KW; d++) {
     hsum((int64_t)d - RAD, ring[d]);
 #pragma unroll
-    for (int i = 0; i < LV; i++) v[i] = add_mod(v[i], ring[d][i], fc.q[i]);
+    for (int t = 0; t < XT; t++)
+#pragma unroll
+      for (int i = 0; i < LV; i++) v[t][i] += ring[d][t][i];
   }
   const uint64_t out_stride = (uint64_t)2 * (LV - 1) * N;
   const uint64_t out_base = (uint64_t)poly * (LV - 1) * N + j;
+  const double ql = fc.q[LV - 1], qlinv = fc.qinv[LV - 1];
   for (uint32_t y0 = 0; y0 < H; y0 += KW) {
 #pragma unroll
     for (int s = 0; s < KW; s++) {
       const uint32_t y = y0 + s;
       if (y >= H) break;
-      // emit row y: multiply by K, then rescale by q_last
-      uint64_t m[LV];
 #pragma unroll
-      for (int i = 0; i < LV; i++) m[i] = mul_shoup(v[i], fc.K[i], fc.Kp[i], fc.q[i]);
-      const uint64_t r = add_mod(m[LV - 1], fc.h, fc.qlast);
-      uint64_t *o = out + ((uint64_t)y * W + x) * out_stride + out_base;
+      for (int t = 0; t < XT; t++) {
+        if (x0 + t >= W) break;
+        const double r = canon(mulmod(v[t][LV - 1], fc.K[LV - 1], ql, qlinv) + fc.h, ql, qlinv);
+        uint64_t *o = out + ((uint64_t)y * W + x0 + t) * out_stride + out_base;
 #pragma unroll
-      for (int i = 0; i < LV - 1; i++) {
-        const uint64_t qi = fc.q[i];
-        const uint64_t ri = r >= qi ? r - qi : r;
-        const uint64_t num = sub_mod(add_mod(m[i], fc.h_mod[i], qi), ri, qi);
-        o[(size_t)i * N] = mul_shoup(num, fc.qlinv[i], fc.qlinv_p[i], qi);
+        for (int i = 0; i < LV - 1; i++) {
+          const double m = mulmod(v[t][i], fc.K[i], fc.q[i], fc.qinv[i]);
+          const double z = mulmod(m + fc.h - r, fc.qlinv[i], fc.q[i], fc.qinv[i]);
+          __builtin_nontemporal_store(f64_to_u64(canon(z, fc.q[i], fc.qinv[i])), o + (size_t)i * N);
+        }
       }
       // slide the window: ring slot s holds row y - RAD; replace it by row y + RAD + 1
       if (y + 1 < H) {
-        uint64_t nh[LV];
+        double nh[XT][LV];
         hsum((int64_t)y + RAD + 1, nh);
 #pragma unroll
-        for (int i = 0; i < LV; i++) {
-          v[i] = add_mod(sub_mod(v[i], ring[s][i], fc.q[i]), nh[i], fc.q[i]);
-          ring[s][i] = nh[i];
-        }
+        for (int t = 0; t < XT; t++)
+#pragma unroll
+          for (int i = 0; i < LV; i++) {
+            v[t][i] = (v[t][i] - ring[s][t][i]) + nh[t][i];
+            ring[s][t][i] = nh[t][i];
+          }
       }
     }
   }
@@ -263,13 +292,23 @@ hipError_t launch_rescale(const ckks_ctx *c, const uint64_t *a, uint64_t *out, u
   return hipGetLastError();
 }
 
+// Output columns per thread: enough to share the k - 1 halo columns, few enough that the
+// ring of k * XT * LV sums stays in registers.
+template <int KW, int LV>
+constexpr int filter_xt() {
+  return KW * LV <= 16 ? 2 : 1;
+}
+
 template <int KW, int LV>
 static hipError_t filter_t(const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, int log_n,
                            const FilterConsts &fc, hipStream_t st) {
-  const uint64_t threads = (uint64_t)W * 2 * ((uint64_t)1 << log_n);
-  const uint64_t blocks = (threads + kRowThreads - 1) / kRowThreads;
-  hipLaunchKernelGGL((k_mean_filter<KW, LV>), dim3((uint32_t)blocks), dim3(kRowThreads), 0, st, in, out, H, W, log_n,
-                     fc);
+  constexpr int XT = filter_xt<KW, LV>();
+  const uint64_t tiles = ((uint64_t)W + XT - 1) / XT;
+  const uint64_t groups = (tiles + kFilterWaves - 1) / kFilterWaves;
+  const uint64_t blocks = groups * 2 * (((uint64_t)1 << log_n) / 64);
+  if (blocks > 0xffffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_mean_filter<KW, LV, XT>), dim3((uint32_t)blocks), dim3(kRowThreads), 0, st, in, out, H, W,
+                     log_n, (uint32_t)groups, fc);
   return hipGetLastError();
 }
 
@@ -288,15 +327,22 @@ static hipError_t filter_level(int level, const uint64_t *in, uint64_t *out, uin
   }
 }
 
+static double centered_double(uint64_t x, uint64_t q) {
+  return x > q / 2 ? -(double)(q - x) : (double)x;
+}
+
 hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
                               uint32_t k, int level, const uint64_t *K, hipStream_t st) {
   FilterConsts fc{};
+  const uint64_t qlast = c->prm.q[(size_t)level - 1];
   for (int i = 0; i < level; i++) {
-    fc.q[i] = c->prm.q[(size_t)i];
-    fc.K[i] = K[i];
-    fc.Kp[i] = host::shoup_companion(K[i], fc.q[i]);
+    const uint64_t qi = c->prm.q[(size_t)i];
+    fc.q[i] = (double)qi;
+    fc.qinv[i] = 1.0 / (double)qi;
+    fc.K[i] = centered_double(K[i] % qi, qi);
+    if (i < level - 1) fc.qlinv[i] = centered_double(host::inv_mod(qlast % qi, qi), qi);
   }
-  rescale_consts(c, level, fc.q, fc.h_mod, fc.qlinv, fc.qlinv_p, &fc.qlast, &fc.h);
+  fc.h = (double)(qlast / 2);
   const int log_n = c->prm.log_n;
   switch (k) {
     case 1: return filter_level<1>(level, in, out, H, W, log_n, fc, st);

@@ -11,6 +11,7 @@
 //
 // Bounds (q < 2^50, 1/q rounded to nearest):
 //   reduce(x):     |x| < 2^52      ->  x' = x (mod q), |x'| <= q/2 + 1
+//                  |x| < 2^53      ->  x' = x (mod q), |x'| <= q/2 + 2 (x an exact integer)
 //   mulmod(a, w):  |a*w/q| < 2^51  ->  r = a*w (mod q), |r| <= q/2 + |a*w| 2^-52 + 1
 // The NTT keeps every value below 2^51 in magnitude by reducing after the stages the
 // host selects (see host_math.cpp), which satisfies both preconditions.
@@ -70,6 +71,23 @@ CKKS_HD void gs_butterfly(double &X, double &Y, double W, double q, double qinv)
   const double d = X - Y;
   X = X + Y;
   Y = mulmod(d, W, q, qinv);
+}
+
+// ---------------------------------------------------------------------------
+// conversions between canonical uint64 residues (< 2^53) and exact doubles
+// ---------------------------------------------------------------------------
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kTwoM32 = 1.0 / 4294967296.0;
+
+CKKS_HD double u64_to_f64(uint64_t x) {
+  return __builtin_fma((double)(uint32_t)(x >> 32), kTwo32, (double)(uint32_t)x);
+}
+
+// x integer-valued in [0, 2^53)
+CKKS_HD uint64_t f64_to_u64(double x) {
+  const uint32_t hi = (uint32_t)(x * kTwoM32);  // truncation = floor for x >= 0
+  const uint32_t lo = (uint32_t)__builtin_fma(-(double)hi, kTwo32, x);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // ---------------------------------------------------------------------------
