@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--ntt-width", type=int, default=0, help="values per NTT thread (16 or 32; 0 = library default)")
+    ap.add_argument("--serving-jobs", type=int, default=200,
+                    help="jobs per load point of the serving measurement (0 = skip it)")
+    ap.add_argument("--serving-budget-gb", type=float, default=160.0, help="device bytes the server may hold")
     return ap.parse_args()
 
 
@@ -100,6 +103,70 @@ def cpu_baseline(cfg, img, sample):
                   "and decryption (%d host threads, caches prebuilt)" % (sample, threads),
         "phase_s": {k2: round(v, 3) for k2, v in t.items()},
     }
+
+
+def serving_bench(P, W, n_jobs, budget_gb):
+    """Serving workload: Poisson arrivals of encrypt (full value cache) -> 3x3 mean filter ->
+    decrypt jobs on N=8192 / 4x50-bit; closed-loop saturation first, then open-loop
+    arrivals at 0.5, 0.8 and 0.95 of it; latency = host clock from submission to the
+    decrypted pixels being in host memory."""
+    import torch
+
+    cfg = 4
+    c = W.CONFIGS[cfg]
+    e = c.extras
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale, device=0)
+    ctx.keygen(W.keygen_seed(cfg))
+    cache = ctx.cache_build(P.CKKS_CACHE_VALUE_FULL, zero_pool=e["pool"], seed=W.cache_seed(cfg))
+    torch.cuda.synchronize()
+    gaps, imgs = W.serving_jobs(e["seed"], n_jobs, e["lo"], e["hi"])
+    px_total = int(sum(im.size for im in imgs))
+    budget = int(budget_gb * 1e9)
+    max_job = max(P.job_bytes(ctx, *im.shape, e["k"]) for im in imgs)
+    srv = P.Server(ctx, budget, max_inflight=8, filter_k=e["k"], cache=cache,
+                   max_job_pixels=max(im.size for im in imgs))
+
+    def run(arrivals):
+        t0 = time.perf_counter()
+        done = []
+        for i, im in enumerate(imgs):
+            if arrivals is not None:
+                while True:
+                    dt = t0 + arrivals[i] - time.perf_counter()
+                    if dt <= 0:
+                        break
+                    done += srv.poll(64, 0)
+                    time.sleep(min(dt, 5e-4))
+            srv.submit(im, W.job_seed(cfg, i))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        done += srv.poll(len(imgs) + 64, 0)
+        assert len(done) == len(imgs) and all(r["status"] == 0 for r in done)
+        lat = np.array([(r["t_done_us"] - r["t_submit_us"]) / 1e3 for r in done])
+        return wall, lat
+
+    run(None)  # warm-up (pool allocations, pinned staging)
+    wall, lat = run(None)
+    sat_qps = len(imgs) / wall
+    out = {"jobs_per_point": len(imgs), "pixels_per_job_mean": round(px_total / len(imgs), 1),
+           "max_job_GB": round(max_job / 1e9, 2), "budget_GB": round(budget / 1e9, 1), "slots": 8,
+           "closed_loop": {"qps": round(sat_qps, 2), "px_per_s": round(px_total / wall),
+                           "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                           "p99_ms": round(float(np.percentile(lat, 99)), 2)},
+           "open_loop": []}
+    for load in (0.5, 0.8, 0.95):
+        qps = load * sat_qps
+        wall, lat = run(np.cumsum(gaps) / qps)
+        out["open_loop"].append({"load": load, "qps": round(qps, 2), "px_per_s": round(px_total / wall),
+                                 "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                                 "p99_ms": round(float(np.percentile(lat, 99)), 2)})
+    st = srv.stats()
+    out["peak_inflight_jobs"] = st["peak_inflight_jobs"]
+    out["peak_inflight_GB"] = round(st["peak_inflight_bytes"] / 1e9, 2)
+    srv.close()
+    cache.close()
+    ctx.close()
+    return out
 
 
 def main():
@@ -244,6 +311,12 @@ def main():
         "filter_decrypt_max_err": ok,
         "roofline": roofline,
     }
+    if args.serving_jobs > 0:
+        del ct, flt, dec, radix, value
+        ctx.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(cfg, img, args.cpu_sample)
     print(json.dumps(out))

@@ -247,6 +247,70 @@ int ckks_decrypt_pixels(ckks_ctx *ctx, const ckks_ct_batch *in, double *d_out, v
 /* Wait for all work enqueued on `stream` and report any asynchronous device error. */
 int ckks_stream_sync(ckks_ctx *ctx, void *stream);
 
+/* ---- serving runtime ----
+ * A server runs whole image jobs -- encrypt every pixel (plain or cached, Sec. 2.2.2 /
+ * Sec. 3.2), apply the k x k mean filter (Sec. 4.4.1), decrypt (Sec. 2.2.2) -- for
+ * requests that arrive while earlier ones are still on the GPU.  A dispatcher thread
+ * owned by the server admits queued jobs in arrival order as soon as one of
+ * `max_inflight` slots (each a HIP stream of its own) is free and a contiguous range of
+ * the job's device bytes is free in the server's arena (one device allocation of
+ * `hbm_budget_bytes` made at creation).  Admitted jobs run concurrently on their streams.
+ * Job bytes = align(n) + n*S(L) + n*S(L-1) + align(8n) for n = H*W pixels and
+ * S(l) = ckks_ct_bytes(ctx, l) (pixels, ciphertexts, filtered ciphertexts, decrypted
+ * values); cached encryption also takes its small per-pixel metadata (12 bytes per pixel)
+ * from the stream-ordered pool.  A job's results do not depend on which other jobs run
+ * beside it: its ciphertexts are fixed by (job_seed, first_index) and every kernel's
+ * result is independent of the launch that computes it.
+ */
+typedef struct ckks_server ckks_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes;  /* arena size; jobs larger than this are refused at submission */
+  uint32_t max_inflight;      /* slots (streams), 1..64 */
+  uint32_t filter_k;          /* mean-filter window: 1, 3, 5, 7; 0 = no filter (decrypt the encryption) */
+  const ckks_cache *cache;    /* cache for encryption, NULL = plain encryption; must outlive the server */
+  uint64_t max_job_pixels;    /* pinned staging sized for this many pixels per slot at creation (0 = on demand) */
+} ckks_server_config;
+
+typedef struct {
+  uint64_t job_id;
+  int32_t status;             /* CKKS_OK or the CKKS_E* code of the failed step */
+  uint32_t height, width;
+  double t_submit_us;         /* host steady clock, microseconds since the server was created */
+  double t_admit_us;
+  double t_done_us;           /* when the dispatcher saw the job's last copy complete */
+  double gpu_ms;              /* device time from the job's first to its last operation */
+} ckks_job_result;
+
+typedef struct {
+  uint64_t submitted, completed, failed, queued, inflight;
+  uint64_t arena_bytes, inflight_bytes, peak_inflight_bytes;
+  uint32_t peak_inflight_jobs, reserved;
+} ckks_server_stats;
+
+/* Creates a server and starts its dispatcher.  Needs keys on ctx; ctx (and cache) must
+ * outlive the server.  ENOMEM if the arena cannot be allocated. */
+int ckks_server_create(ckks_ctx *ctx, const ckks_server_config *cfg, ckks_server **out);
+
+/* Queues one job of H*W pixels (host_px, row-major uint8).  host_px is copied before the
+ * call returns; host_out (H*W doubles, the decrypted filtered pixels) must stay valid
+ * until the job's result has been returned by ckks_server_poll.  Ciphertext t uses Philox
+ * index first_index + t under job_seed.  ENOMEM_BUDGET if the job can never fit. */
+int ckks_server_submit(ckks_server *srv, const uint8_t *host_px, uint32_t H, uint32_t W, const uint64_t job_seed[2],
+                       uint64_t first_index, double *host_out, uint64_t *job_id);
+
+/* Returns up to `max` finished jobs (oldest first), waiting up to wait_ms milliseconds
+ * (0 = do not wait, negative = until at least one is available or nothing is pending). */
+int ckks_server_poll(ckks_server *srv, ckks_job_result *out, uint32_t max, uint32_t *n_out, int32_t wait_ms);
+
+/* Blocks until every submitted job has finished (results stay available to poll). */
+int ckks_server_drain(ckks_server *srv);
+
+int ckks_server_stats_get(ckks_server *srv, ckks_server_stats *out);
+
+/* Stops the dispatcher after the running jobs finish; queued jobs are dropped. */
+void ckks_server_destroy(ckks_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,24 @@ class ckks_cache_desc_t(C.Structure):
                 ("zero_pool", C.c_uint32)]
 
 
+class ckks_server_config_t(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("filter_k", C.c_uint32),
+                ("cache", C.c_void_p), ("max_job_pixels", C.c_uint64)]
+
+
+class ckks_job_result_t(C.Structure):
+    _fields_ = [("job_id", C.c_uint64), ("status", C.c_int32), ("height", C.c_uint32), ("width", C.c_uint32),
+                ("t_submit_us", C.c_double), ("t_admit_us", C.c_double), ("t_done_us", C.c_double),
+                ("gpu_ms", C.c_double)]
+
+
+class ckks_server_stats_t(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("queued", C.c_uint64), ("inflight", C.c_uint64), ("arena_bytes", C.c_uint64),
+                ("inflight_bytes", C.c_uint64), ("peak_inflight_bytes", C.c_uint64),
+                ("peak_inflight_jobs", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 _lib = None
 
 _SIGS = {
@@ -87,6 +105,14 @@ _SIGS = {
                                    C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_decrypt_pixels": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_void_p, C.c_void_p]),
     "ckks_stream_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ckks_server_create": (C.c_int, [C.c_void_p, C.POINTER(ckks_server_config_t), C.POINTER(C.c_void_p)]),
+    "ckks_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64),
+                                     C.c_uint64, C.c_void_p, C.POINTER(C.c_uint64)]),
+    "ckks_server_poll": (C.c_int, [C.c_void_p, C.POINTER(ckks_job_result_t), C.c_uint32, C.POINTER(C.c_uint32),
+                                   C.c_int32]),
+    "ckks_server_drain": (C.c_int, [C.c_void_p]),
+    "ckks_server_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ckks_server_stats_t)]),
+    "ckks_server_destroy": (None, [C.c_void_p]),
 }
 
 
@@ -379,6 +405,80 @@ class Cache:
     def close(self):
         if getattr(self, "handle", None):
             lib().ckks_cache_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def job_bytes(ctx: Context, H: int, W: int, filter_k: int) -> int:
+    """Arena bytes a server job of H x W pixels takes (pixels, ciphertexts, filtered
+    ciphertexts if filter_k, decrypted values), as the server's admission counts them."""
+    n = H * W
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    b = al(n) + n * ctx.ct_bytes(ctx.L) + al(8 * n)
+    if filter_k:
+        b += n * ctx.ct_bytes(ctx.L - 1)
+    return b
+
+
+class Server:
+    """Serving runtime over a context: jobs of encrypt -> k x k mean filter -> decrypt,
+    admitted in arrival order by device bytes into an arena of `hbm_budget_bytes`, at most
+    `max_inflight` running at once, each on its own stream."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_inflight: int = 4, filter_k: int = 3,
+                 cache: "Cache | None" = None, max_job_pixels: int = 0):
+        cfg = ckks_server_config_t(int(hbm_budget_bytes), int(max_inflight), int(filter_k),
+                                   cache.handle if cache is not None else None, int(max_job_pixels))
+        h = C.c_void_p()
+        _check(lib().ckks_server_create(ctx.handle, C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self.cache = cache
+        self.filter_k = int(filter_k)
+        self._outputs = {}  # job id -> (pixels copy owner, output array): kept alive until polled
+
+    def job_bytes(self, H: int, W: int) -> int:
+        return job_bytes(self.ctx, H, W, self.filter_k)
+
+    def submit(self, img, seed, first_index: int = 0) -> int:
+        img = np.ascontiguousarray(img, dtype=np.uint8)
+        H, W = img.shape
+        out = np.empty(H * W, dtype=np.float64)
+        jid = C.c_uint64(0)
+        _check(lib().ckks_server_submit(self.handle, img.ctypes.data, H, W, _seed(seed), int(first_index),
+                                        out.ctypes.data, C.byref(jid)))
+        self._outputs[int(jid.value)] = out
+        return int(jid.value)
+
+    def poll(self, max_results: int = 64, wait_ms: int = 0):
+        """List of finished jobs: dicts with id, status, times (us) and the decrypted pixels."""
+        buf = (ckks_job_result_t * max(1, max_results))()
+        n = C.c_uint32(0)
+        _check(lib().ckks_server_poll(self.handle, buf, max_results, C.byref(n), int(wait_ms)))
+        res = []
+        for r in buf[: n.value]:
+            out = self._outputs.pop(int(r.job_id))
+            res.append({"id": int(r.job_id), "status": int(r.status), "H": int(r.height), "W": int(r.width),
+                        "t_submit_us": r.t_submit_us, "t_admit_us": r.t_admit_us, "t_done_us": r.t_done_us,
+                        "gpu_ms": r.gpu_ms, "pixels": out.reshape(r.height, r.width)})
+        return res
+
+    def drain(self):
+        _check(lib().ckks_server_drain(self.handle))
+
+    def stats(self) -> dict:
+        st = ckks_server_stats_t()
+        _check(lib().ckks_server_stats_get(self.handle, C.byref(st)))
+        return {f: int(getattr(st, f)) for f, _ in ckks_server_stats_t._fields_ if f != "reserved"}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ckks_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -129,6 +129,18 @@ int const_multiplier(const ckks_ctx *c, uint32_t level, double scale, double cst
 
 }  // namespace
 
+namespace ckks {
+int api_fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+}  // namespace ckks
+
 extern "C" {
 
 const char *ckks_last_error(void) { return g_err.c_str(); }

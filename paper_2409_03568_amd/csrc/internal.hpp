@@ -84,6 +84,9 @@ struct ckks_cache {
 
 namespace ckks {
 
+// Records a message for ckks_last_error() (thread-local) and returns `code`.
+int api_fail(int code, const char *fmt, ...);
+
 // Launchers (return a hipError_t; enqueue on `stream`).
 hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
 hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream);

@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     const uint64_t *c1 = c0 + (size_t)level * N;
     double x[R];
 #pragma unroll
-    for (int r = 0; r < R; r++) x[r] = (double)c1[tid + T * r];
+    for (int r = 0; r < R; r++) x[r] = u64_to_f64(__builtin_nontemporal_load(c1 + tid + T * r));
     ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd, q, qinv);
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = mulmod(x[r], dt.s_hat[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int j = tid + T * r;
-      const double d = center(x[r] + (double)c0[j], q, qinv);
+      const double d = center(x[r] + u64_to_f64(__builtin_nontemporal_load(c0 + j)), q, qinv);
       acc = __builtin_fma(d, dt.cosj[j], acc);
     }
     // workgroup sum in a fixed order: wave butterflies, then the waves in sequence

@@ -67,6 +67,12 @@ CONFIGS = {
               "2 digits) vs value-cache (top-64, pool 256) encrypt; 3x3 mean filter; decrypt",
               13, 4, 50, 40, extras=dict(H=256, W=256, image="zipf", seed=2, base=16, digits=2, topk=64,
                                          pool=256, k=3)),
+    3: Config("N=8192, 4x50-bit primes, scale 2^40; 64 RGB images, sides log-uniform in 32..512; full value "
+              "cache; brightness +b per image; decrypt", 13, 4, 50, 40,
+              extras=dict(count=64, lo=32, hi=512, seed=3, pool=256)),
+    4: Config("N=8192, 4x50-bit primes, scale 2^40; Poisson arrivals of encrypt -> 3x3 mean filter -> decrypt "
+              "jobs, Zipf(1.1) grayscale images with sides log-uniform in 32..384", 13, 4, 50, 40,
+              extras=dict(lo=32, hi=384, seed=4, pool=256, k=3)),
     5: Config("N=4096, 3x36-bit primes, scale 2^30; 512x512 Zipf(1.1) image; plain / radix / value encrypt; "
               "5x5 mean filter", 12, 3, 36, 30,
               extras=dict(H=512, W=512, image="zipf", seed=5, base=16, digits=2, topk=64, pool=256, k=5)),
@@ -89,6 +95,18 @@ def batched_rgb_images(seed: int = 3, count: int = 64, lo: int = 32, hi: int = 5
     imgs = [rng.integers(0, 256, (int(h), int(w), 3), dtype=np.uint8) for h, w in zip(H, W)]
     b = rng.integers(-40, 41, count)
     return imgs, b
+
+
+def serving_jobs(seed: int, count: int, lo: int = 32, hi: int = 384):
+    """Unit-rate exponential arrival gaps and grayscale Zipf images with log-uniform sides;
+    the arrival times at rate qps are cumsum(gaps) / qps, so every rate sees the same jobs."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0, size=count)
+    H = log_uniform_sides(rng, count, lo, hi)
+    W = log_uniform_sides(rng, count, lo, hi)
+    pmf = zipf_pmf()
+    imgs = [rng.choice(256, size=(int(h), int(w)), p=pmf).astype(np.uint8) for h, w in zip(H, W)]
+    return gaps, imgs
 
 
 def poisson_arrivals(seed: int, qps: float, count: int, lo: int = 32, hi: int = 384):
