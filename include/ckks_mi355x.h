@@ -247,6 +247,59 @@ int ckks_decrypt_pixels(ckks_ctx *ctx, const ckks_ct_batch *in, double *d_out, v
 /* Wait for all work enqueued on `stream` and report any asynchronous device error. */
 int ckks_stream_sync(ckks_ctx *ctx, void *stream);
 
+/* ---- autotuning ----
+ * Times the NTT kernels (encryption, Sec. 2.2.2: one forward and two inverse
+ * transforms per limb; decryption: one forward and one inverse on limb 0) at each
+ * supported register blocking (16 or 32 values per thread) on trial_cts synthetic
+ * ciphertexts, keeps the faster width for each kernel on this context, and reports the
+ * timings.  The choice changes speed only, never results.  Enqueues on the null stream
+ * and synchronizes; allocates and frees its own scratch buffers.
+ */
+typedef struct {
+  uint32_t encrypt_width, decrypt_width;  /* chosen values per thread */
+  uint32_t trial_cts, reserved;
+  double encrypt_ms[2], decrypt_ms[2];    /* best of 3 runs: [0] 16, [1] 32 values per thread */
+} ckks_tune_report;
+
+int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out);
+
+/* ---- batched images ----
+ * Encrypts many images packed in one flat pixel array (image i = pixels
+ * [seg_end[i-1], seg_end[i])), adds each image's brightness constant b_i
+ * (add_const, Sec. 4.4.2: encode(b_i) in slot 0 of c0), and decrypts every ciphertext
+ * (Sec. 2.2.2) -- the batched form of encrypt -> brighten -> decrypt.  Ciphertexts are
+ * produced chunk by chunk into a ring buffer of chunk_cts ciphertexts owned by the plan
+ * (each fully materialized, all limbs, before it is decrypted), so device memory stays
+ * bounded whatever the batch size.  With a value cache, hits are assembled by the
+ * gather kernel with the brightness fused in, misses by the plain encryption kernel over
+ * a compacted list; without a cache every pixel is plain-encrypted with the brightness
+ * fused in.  Results equal ckks_encrypt_cached / ckks_encrypt_pixels followed by
+ * ckks_add_const and ckks_decrypt_pixels, bit for bit.
+ * With use_graph, the whole chunk sequence is captured once into a HIP graph and
+ * replayed while ckks_batch_run is called again with the same arguments.
+ */
+typedef struct ckks_batch_plan ckks_batch_plan;
+
+typedef struct {
+  uint64_t chunk_cts;  /* ciphertexts per ring-buffer chunk (>= 1) */
+  uint32_t use_graph;  /* 1 = capture the chunk sequence in a HIP graph and replay it */
+  uint32_t reserved;
+} ckks_batch_config;
+
+/* cache: a VALUE_TOPK / VALUE_FULL cache of ctx, or NULL for plain encryption. */
+int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_batch_config *cfg,
+                           ckks_batch_plan **out);
+
+/* d_px: n pixels (device).  host_seg_end: n_seg ascending image ends, the last = n.
+ * host_seg_b: n_seg brightness constants, |b * scale * 2^(1 - log N)| < 2^50.
+ * d_out: n doubles (device), the decrypted pixel + b values.  Ciphertext t uses Philox
+ * index first_index + t.  Enqueued on `stream`. */
+int ckks_batch_run(ckks_batch_plan *plan, const uint8_t *d_px, uint64_t n, const uint64_t *host_seg_end,
+                   const double *host_seg_b, uint32_t n_seg, const uint64_t seed[2], uint64_t first_index,
+                   double *d_out, void *stream);
+
+void ckks_batch_plan_destroy(ckks_batch_plan *plan);
+
 /* ---- serving runtime ----
  * A server runs whole image jobs -- encrypt every pixel (plain or cached, Sec. 2.2.2 /
  * Sec. 3.2), apply the k x k mean filter (Sec. 4.4.1), decrypt (Sec. 2.2.2) -- for

@@ -66,6 +66,15 @@ class ckks_server_stats_t(C.Structure):
                 ("peak_inflight_jobs", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class ckks_tune_report_t(C.Structure):
+    _fields_ = [("encrypt_width", C.c_uint32), ("decrypt_width", C.c_uint32), ("trial_cts", C.c_uint32),
+                ("reserved", C.c_uint32), ("encrypt_ms", C.c_double * 2), ("decrypt_ms", C.c_double * 2)]
+
+
+class ckks_batch_config_t(C.Structure):
+    _fields_ = [("chunk_cts", C.c_uint64), ("use_graph", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 _lib = None
 
 _SIGS = {
@@ -105,6 +114,12 @@ _SIGS = {
                                    C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_decrypt_pixels": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_void_p, C.c_void_p]),
     "ckks_stream_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ckks_autotune": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(ckks_tune_report_t)]),
+    "ckks_batch_plan_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ckks_batch_config_t),
+                                         C.POINTER(C.c_void_p)]),
+    "ckks_batch_run": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_double),
+                                 C.c_uint32, C.POINTER(C.c_uint64), C.c_uint64, C.c_void_p, C.c_void_p]),
+    "ckks_batch_plan_destroy": (None, [C.c_void_p]),
     "ckks_server_create": (C.c_int, [C.c_void_p, C.POINTER(ckks_server_config_t), C.POINTER(C.c_void_p)]),
     "ckks_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64),
                                      C.c_uint64, C.c_void_p, C.POINTER(C.c_uint64)]),
@@ -378,6 +393,14 @@ class Context:
     def stream_sync(self, stream=None):
         _check(lib().ckks_stream_sync(self.handle, _stream(stream)))
 
+    def autotune(self, trial_cts: int = 4096) -> dict:
+        """Time both NTT register blockings for encryption and decryption; keep the faster."""
+        r = ckks_tune_report_t()
+        _check(lib().ckks_autotune(self.handle, int(trial_cts), C.byref(r)))
+        return {"encrypt_width": r.encrypt_width, "decrypt_width": r.decrypt_width, "trial_cts": r.trial_cts,
+                "encrypt_ms": {16: r.encrypt_ms[0], 32: r.encrypt_ms[1]},
+                "decrypt_ms": {16: r.decrypt_ms[0], 32: r.decrypt_ms[1]}}
+
 
 class Cache:
     def __init__(self, handle, ctx: Context, kind: int):
@@ -405,6 +428,44 @@ class Cache:
     def close(self):
         if getattr(self, "handle", None):
             lib().ckks_cache_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """Batched images: flat pixels, per-image brightness, decrypted values; ciphertexts go
+    through a ring buffer of chunk_cts ciphertexts; optional HIP-graph replay."""
+
+    def __init__(self, ctx: Context, cache: "Cache | None", chunk_cts: int, use_graph: bool = False):
+        cfg = ckks_batch_config_t(int(chunk_cts), 1 if use_graph else 0, 0)
+        h = C.c_void_p()
+        _check(lib().ckks_batch_plan_create(ctx.handle, cache.handle if cache is not None else None, C.byref(cfg),
+                                            C.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self.cache = cache
+
+    def run(self, px, seg_end, seg_b, seed, first_index: int = 0, out=None, stream=None):
+        import torch
+
+        n = px.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=px.device)
+        se = np.ascontiguousarray(seg_end, dtype=np.uint64)
+        sb = np.ascontiguousarray(seg_b, dtype=np.float64)
+        _check(lib().ckks_batch_run(self.handle, _ptr(px), n, se.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                    sb.ctypes.data_as(C.POINTER(C.c_double)), len(se), _seed(seed), int(first_index),
+                                    _ptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ckks_batch_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

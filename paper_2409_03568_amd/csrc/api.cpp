@@ -215,7 +215,7 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   // the transforms' lazy-reduction schedule is compiled per class of prime sizes
   c->rc = qmax < 1099511627776.0 ? 0 : 1;
   // values per NTT thread: 16 (twice the threads, half the registers) measured faster
-  c->logr = 4;
+  c->logr_enc = c->logr_dec = 4;
   hipError_t e = hipSuccess;
   DevTables &d = c->dev;
   if (e == hipSuccess) e = dev_alloc(&d.tw_fwd, (size_t)L * N);
@@ -260,7 +260,7 @@ int ckks_context_set_ntt_width(ckks_ctx *ctx, uint32_t values_per_thread) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (values_per_thread != 16 && values_per_thread != 32) return fail(CKKS_EINVAL, "values_per_thread must be 16 or 32");
-  ctx->logr = values_per_thread == 16 ? 4 : 5;
+  ctx->logr_enc = ctx->logr_dec = values_per_thread == 16 ? 4 : 5;
   return CKKS_OK;
 }
 
@@ -268,7 +268,7 @@ int ckks_context_get_ntt_width(const ckks_ctx *ctx, uint32_t *values_per_thread)
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (!values_per_thread) return fail(CKKS_EINVAL, "values_per_thread is NULL");
-  *values_per_thread = 1u << ctx->logr;
+  *values_per_thread = 1u << ctx->logr_enc;
   return CKKS_OK;
 }
 
@@ -551,7 +551,7 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
           "counter alloc");
   HIP_TRY(launch_value_meta(ctx, cache, d_px, n, first_index, seed[0], seed[1], meta, miss, counters, hits, st),
           "value meta");
-  HIP_TRY(launch_value_gather(ctx, cache, meta, counters, hits, n, out->data, st), "value gather");
+  HIP_TRY(launch_value_gather(ctx, cache, meta, counters, hits, n, out->data, nullptr, st), "value gather");
   EncJob job;
   job.px = d_px;
   job.list = miss;

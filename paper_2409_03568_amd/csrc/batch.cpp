@@ -1,0 +1,298 @@
+// Batched images (flat pixel index space, ring buffer of ciphertext chunks, HIP graph
+// replay) and the per-context autotuner of the NTT kernels' register blocking.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace ckks;
+
+namespace {
+
+#define BATCH_TRY(expr, what)                                                               \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return api_fail(CKKS_EDEVICE, "%s: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct RunKey {
+  const uint8_t *px = nullptr;
+  uint64_t n = 0;
+  std::vector<uint64_t> seg_end;
+  std::vector<double> seg_b;
+  uint64_t seed[2] = {0, 0};
+  uint64_t first_index = 0;
+  double *out = nullptr;
+  bool operator==(const RunKey &o) const {
+    return px == o.px && n == o.n && seg_end == o.seg_end && seg_b == o.seg_b && seed[0] == o.seed[0] &&
+           seed[1] == o.seed[1] && first_index == o.first_index && out == o.out;
+  }
+};
+
+}  // namespace
+
+struct ckks_batch_plan {
+  ckks_ctx *ctx = nullptr;
+  const ckks_cache *cache = nullptr;
+  ckks_batch_config cfg{};
+  uint64_t *ring = nullptr;      // [chunk][2][L][N]
+  uint32_t *meta = nullptr;      // [chunk]
+  uint32_t *miss = nullptr;      // [chunk]
+  uint32_t *hits = nullptr;      // [chunk]
+  uint32_t *counters = nullptr;  // [2 + pool]
+  uint64_t *seg_end = nullptr;   // [seg_cap]
+  double *seg_b = nullptr;       // [seg_cap]
+  uint32_t seg_cap = 0;
+  hipStream_t cap = nullptr;     // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool have_key = false;
+  RunKey key;
+};
+
+namespace {
+
+void drop_graph(ckks_batch_plan *p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->have_key = false;
+}
+
+void free_plan(ckks_batch_plan *p) {
+  drop_graph(p);
+  void *ptrs[] = {p->ring, p->meta, p->miss, p->hits, p->counters, p->seg_end, p->seg_b};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  delete p;
+}
+
+// Enqueues every chunk of one run on stream st (which may be capturing).
+hipError_t enqueue_chunks(ckks_batch_plan *p, const RunKey &k, uint32_t n_seg, hipStream_t st) {
+  const ckks_ctx *c = p->ctx;
+  const uint64_t chunk = p->cfg.chunk_cts;
+  for (uint64_t first = 0; first < k.n; first += chunk) {
+    const uint64_t cnt = k.n - first < chunk ? k.n - first : chunk;
+    EncJob job;
+    job.px = k.px + first;
+    job.n = cnt;
+    job.first_index = k.first_index + first;
+    job.seed0 = k.seed[0];
+    job.seed1 = k.seed[1];
+    job.out = p->ring;
+    job.seg_end = p->seg_end;
+    job.seg_b = p->seg_b;
+    job.n_seg = n_seg;
+    job.seg_base = first;
+    job.bright_scale = ldexp(c->scale, 1 - c->prm.log_n);
+    hipError_t e;
+    if (p->cache) {
+      e = launch_value_meta(c, p->cache, job.px, cnt, job.first_index, job.seed0, job.seed1, p->meta, p->miss,
+                            p->counters, p->hits, st);
+      if (e == hipSuccess) e = launch_value_gather(c, p->cache, p->meta, p->counters, p->hits, cnt, p->ring, &job, st);
+      job.list = p->miss;
+      job.list_count = p->counters;
+      if (e == hipSuccess) e = launch_encrypt(c, job, cnt < kListGrid ? cnt : kListGrid, st);
+    } else {
+      e = launch_encrypt(c, job, cnt < (1u << 24) ? cnt : (1u << 24), st);
+    }
+    if (e == hipSuccess) e = launch_decrypt(c, p->ring, cnt, c->prm.L, c->scale, k.out + first, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_batch_config *cfg,
+                           ckks_batch_plan **out) {
+  if (!ctx || !cfg || !out) return api_fail(CKKS_EINVAL, "ctx/cfg/out is NULL");
+  *out = nullptr;
+  if (!ctx->has_keys) return api_fail(CKKS_ESTATE, "no keys on the context");
+  if (cfg->chunk_cts < 1 || cfg->chunk_cts > 0xFFFFFFFFull) return api_fail(CKKS_EINVAL, "chunk_cts must be 1..2^32-1");
+  if (cache && cache->ctx != ctx) return api_fail(CKKS_ECACHE, "cache belongs to another context");
+  if (cache && cache->kind == CKKS_CACHE_RADIX) return api_fail(CKKS_EUNSUPPORTED, "batches take a value cache or none");
+  DeviceScope g(ctx->device);
+  ckks_batch_plan *p = new ckks_batch_plan;
+  p->ctx = ctx;
+  p->cache = cache;
+  p->cfg = *cfg;
+  const uint64_t chunk = cfg->chunk_cts;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->ring), chunk * ckks_ct_bytes(ctx, (uint32_t)ctx->prm.L));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->meta), chunk * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->miss), chunk * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->hits), chunk * sizeof(uint32_t));
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void **>(&p->counters), (2 + (size_t)(cache ? cache->pool : 0)) * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return api_fail(CKKS_ENOMEM, "batch plan allocation: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return CKKS_OK;
+}
+
+int ckks_batch_run(ckks_batch_plan *p, const uint8_t *d_px, uint64_t n, const uint64_t *host_seg_end,
+                   const double *host_seg_b, uint32_t n_seg, const uint64_t seed[2], uint64_t first_index,
+                   double *d_out, void *stream) {
+  if (!p || !seed) return api_fail(CKKS_EINVAL, "plan/seed is NULL");
+  if (n == 0) return CKKS_OK;
+  if (!d_px || !d_out || !host_seg_end || !host_seg_b) return api_fail(CKKS_EINVAL, "NULL buffer");
+  if (n_seg < 1) return api_fail(CKKS_EINVAL, "need at least one image");
+  ckks_ctx *c = p->ctx;
+  const double bscale = ldexp(c->scale, 1 - c->prm.log_n);
+  for (uint32_t i = 0; i < n_seg; i++) {
+    if (i && host_seg_end[i] < host_seg_end[i - 1]) return api_fail(CKKS_EINVAL, "seg_end must be ascending");
+    if (!(fabs(host_seg_b[i] * bscale) < 1125899906842624.0))  // 2^50
+      return api_fail(CKKS_EINVAL, "brightness %g too large for the fused encoding", host_seg_b[i]);
+  }
+  if (host_seg_end[n_seg - 1] != n) return api_fail(CKKS_EINVAL, "last seg_end must equal n");
+  DeviceScope g(c->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  RunKey k;
+  k.px = d_px;
+  k.n = n;
+  k.seg_end.assign(host_seg_end, host_seg_end + n_seg);
+  k.seg_b.assign(host_seg_b, host_seg_b + n_seg);
+  k.seed[0] = seed[0];
+  k.seed[1] = seed[1];
+  k.first_index = first_index;
+  k.out = d_out;
+  const bool same = p->have_key && p->key == k;
+  if (!same) {
+    // the segment tables may still be read by work enqueued for an earlier run: let it
+    // finish before they are replaced
+    BATCH_TRY(hipStreamSynchronize(st), "stream synchronize");
+    drop_graph(p);
+    if (n_seg > p->seg_cap) {
+      if (p->seg_end) (void)hipFree(p->seg_end);
+      if (p->seg_b) (void)hipFree(p->seg_b);
+      p->seg_end = nullptr;
+      p->seg_b = nullptr;
+      p->seg_cap = 0;
+      BATCH_TRY(hipMalloc(reinterpret_cast<void **>(&p->seg_end), n_seg * sizeof(uint64_t)), "segment alloc");
+      BATCH_TRY(hipMalloc(reinterpret_cast<void **>(&p->seg_b), n_seg * sizeof(double)), "segment alloc");
+      p->seg_cap = n_seg;
+    }
+    BATCH_TRY(hipMemcpy(p->seg_end, host_seg_end, n_seg * sizeof(uint64_t), hipMemcpyHostToDevice), "segment upload");
+    BATCH_TRY(hipMemcpy(p->seg_b, host_seg_b, n_seg * sizeof(double), hipMemcpyHostToDevice), "segment upload");
+  }
+  if (!p->cfg.use_graph || !same) {
+    // eager launch: the first run with new arguments (and every run without graphs)
+    BATCH_TRY(enqueue_chunks(p, k, n_seg, st), "batch launch");
+    p->key = k;
+    p->have_key = true;
+    if (!p->cfg.use_graph) return CKKS_OK;
+    // record the same sequence for the next runs with these arguments (capture does not execute it)
+    BATCH_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    const hipError_t e = enqueue_chunks(p, k, n_seg, p->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(p->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      p->have_key = false;
+      return api_fail(CKKS_EDEVICE, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    p->graph = graph;
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+      drop_graph(p);
+      return api_fail(CKKS_EDEVICE, "graph instantiate failed");
+    }
+    return CKKS_OK;
+  }
+  BATCH_TRY(hipGraphLaunch(p->exec, st), "graph launch");
+  return CKKS_OK;
+}
+
+void ckks_batch_plan_destroy(ckks_batch_plan *p) {
+  if (!p) return;
+  DeviceScope g(p->ctx->device);
+  (void)hipDeviceSynchronize();
+  free_plan(p);
+}
+
+int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
+  if (!ctx || !out) return api_fail(CKKS_EINVAL, "ctx/out is NULL");
+  if (!ctx->has_keys) return api_fail(CKKS_ESTATE, "no keys on the context");
+  if (trial_cts < 1 || trial_cts > (1u << 20)) return api_fail(CKKS_EINVAL, "trial_cts must be 1..2^20");
+  DeviceScope g(ctx->device);
+  const uint32_t L = (uint32_t)ctx->prm.L;
+  uint8_t *px = nullptr;
+  uint64_t *cts = nullptr;
+  double *dec = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&px), trial_cts);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&cts), (uint64_t)trial_cts * ckks_ct_bytes(ctx, L));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&dec), (uint64_t)trial_cts * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(px, 0x5a, trial_cts);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int keep_enc = ctx->logr_enc, keep_dec = ctx->logr_dec;
+  double enc_ms[2] = {INFINITY, INFINITY}, dec_ms[2] = {INFINITY, INFINITY};
+  for (int w = 0; w < 2 && e == hipSuccess; w++) {
+    ctx->logr_enc = ctx->logr_dec = 4 + w;
+    EncJob job;
+    job.px = px;
+    job.n = trial_cts;
+    job.seed0 = 0x7u;
+    job.seed1 = 0x70u;
+    job.out = cts;
+    for (int rep = 0; rep < 4 && e == hipSuccess; rep++) {  // first run warms up
+      float ms = 0.f;
+      e = hipEventRecord(e0, nullptr);
+      if (e == hipSuccess) e = launch_encrypt(ctx, job, trial_cts, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && rep) enc_ms[w] = fmin(enc_ms[w], ms);
+      if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+      if (e == hipSuccess) e = launch_decrypt(ctx, cts, trial_cts, (int)L, ctx->scale, dec, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && rep) dec_ms[w] = fmin(dec_ms[w], ms);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (px) (void)hipFree(px);
+  if (cts) (void)hipFree(cts);
+  if (dec) (void)hipFree(dec);
+  if (e != hipSuccess) {
+    ctx->logr_enc = keep_enc;
+    ctx->logr_dec = keep_dec;
+    return api_fail(CKKS_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  }
+  ctx->logr_enc = enc_ms[1] < enc_ms[0] ? 5 : 4;
+  ctx->logr_dec = dec_ms[1] < dec_ms[0] ? 5 : 4;
+  out->encrypt_width = 1u << ctx->logr_enc;
+  out->decrypt_width = 1u << ctx->logr_dec;
+  out->trial_cts = trial_cts;
+  out->reserved = 0;
+  for (int w = 0; w < 2; w++) {
+    out->encrypt_ms[w] = enc_ms[w];
+    out->decrypt_ms[w] = dec_ms[w];
+  }
+  return CKKS_OK;
+}
+
+}  // extern "C"

@@ -9,6 +9,8 @@
 #include "../../include/ckks_mi355x.h"
 #include "host_math.hpp"
 
+#define CKKS_SEG_HD __host__ __device__
+
 namespace ckks {
 
 constexpr int kMaxL = 16;
@@ -50,7 +52,28 @@ struct EncJob {
   uint64_t first_index = 0;
   uint64_t seed0 = 0, seed1 = 0;
   uint64_t *out = nullptr;  // [n][2][L][N]
+  // Optional brightness (Sec. 4.4.2) fused into c0: item i belongs to image
+  // upper_bound(seg_end, seg_base + i) and gets encode(seg_b[image]) added in slot 0,
+  // i.e. rint(seg_b[image] * bright_scale * cos(pi j / N)) with bright_scale = scale * 2^(1 - log N).
+  const uint64_t *seg_end = nullptr;
+  const double *seg_b = nullptr;
+  uint32_t n_seg = 0;
+  uint64_t seg_base = 0;
+  double bright_scale = 0.0;
 };
+
+// Image of flat pixel index g: the first i with g < seg_end[i] (seg_end ascending, last = total).
+CKKS_SEG_HD inline uint32_t segment_of(const uint64_t *seg_end, uint32_t n_seg, uint64_t g) {
+  uint32_t lo = 0, hi = n_seg - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (g < seg_end[mid])
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
 
 }  // namespace ckks
 
@@ -59,7 +82,8 @@ struct ckks_ctx {
   ckks::host::Resolved prm;
   int N = 0;
   double scale = 0;
-  int logr = 5;  // 2^logr values per thread in the NTT kernels (4 or 5)
+  int logr_enc = 4;  // 2^logr values per thread in the encryption / key kernels (4 or 5)
+  int logr_dec = 4;  // the same for decryption
   int rc = 1;    // reduction class of the primes: 0 if all q < 2^40, else 1 (q < 2^50)
   ckks::LimbConsts lc{};
   ckks::LimbConsts *d_lc = nullptr;  // device copy of lc (kernels read it with scalar loads)
@@ -114,7 +138,7 @@ hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const u
                              uint32_t *miss_list, uint32_t *counters, uint32_t *hits, hipStream_t stream);
 hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta,
                                const uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
-                               hipStream_t stream);
+                               const EncJob *bright, hipStream_t stream);
 hipError_t launch_radix_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t first_index, uint64_t seed0, uint64_t seed1, int16_t *meta, uint32_t *bad,
                              hipStream_t stream);

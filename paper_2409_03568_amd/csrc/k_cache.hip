@@ -114,15 +114,29 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // out = entry[slot] + pool[u] for cached pixels (missed pixels are written by the plain
-// encryption kernel).  One workgroup per hit-list position (XCD-contiguous logical
-// order), streaming all 2L rows of that ciphertext: the hit list is grouped by pool
-// member, so each XCD works through a few pool entries at a time and they stay in its
-// L2, while the output streams past with non-temporal stores.
+// encryption kernel), plus the optional fused brightness encode(b_image) on c0 (see
+// EncJob).  One workgroup per hit-list position (XCD-contiguous logical order),
+// streaming all 2L rows of that ciphertext: the hit list is grouped by pool member, so
+// each XCD works through a few pool entries at a time and they stay in its L2, while
+// the output streams past with non-temporal stores.
+struct Bright {
+  const uint64_t *seg_end;
+  const double *seg_b;
+  uint32_t n_seg;
+  uint64_t seg_base;
+  double scale;  // scale * 2^(1 - log N)
+  const double *cosj;
+};
+
+__device__ __forceinline__ uint64_t add_encoded(uint64_t z, double fb, double cj, double q, double qinv, uint64_t qi) {
+  return add_mod(z, f64_to_u64(canon(__builtin_rint(fb * cj), q, qinv)), qi);
+}
+
 __global__ void __launch_bounds__(kThreads)
     k_value_gather(const uint64_t *__restrict__ entries, const uint64_t *__restrict__ pool,
                    const uint32_t *__restrict__ meta, const uint32_t *__restrict__ hits,
                    const uint32_t *__restrict__ hit_count, int L, int log_n, const LimbConsts *__restrict__ lcp,
-                   uint64_t *__restrict__ out) {
+                   Bright br, uint64_t *__restrict__ out) {
   const LimbConsts &lc = *lcp;
   const int N = 1 << log_n;
   const uint64_t S = (uint64_t)2 * L * N;
@@ -134,9 +148,24 @@ __global__ void __launch_bounds__(kThreads)
     const u64x2 *pe = reinterpret_cast<const u64x2 *>(entries + (uint64_t)((m & 0xffffu) - 1) * S);
     const u64x2 *pz = reinterpret_cast<const u64x2 *>(pool + (uint64_t)(m >> 16) * S);
     u64x2 *po = reinterpret_cast<u64x2 *>(out + ct * S);
+    const double fb = br.seg_b ? br.seg_b[segment_of(br.seg_end, br.n_seg, br.seg_base + ct)] * br.scale : 0.0;
     for (int pl = 0; pl < 2 * L; pl++) {
-      const uint64_t q = lc.qi[pl % L];
+      const int l = pl % L;
+      const uint64_t q = lc.qi[l];
       const int base = pl * (N / 2);
+      if (pl < L && fb != 0.0) {
+        const double qd = lc.q[l], qinv = lc.qinv[l];
+        const double2 *cs = reinterpret_cast<const double2 *>(br.cosj);
+        for (int i = threadIdx.x; i < N / 2; i += kThreads) {
+          const u64x2 a = pe[base + i], b = pz[base + i];
+          const double2 c = cs[i];
+          u64x2 z;
+          z.x = add_encoded(add_mod(a.x, b.x, q), fb, c.x, qd, qinv, q);
+          z.y = add_encoded(add_mod(a.y, b.y, q), fb, c.y, qd, qinv, q);
+          __builtin_nontemporal_store(z, po + base + i);
+        }
+        continue;
+      }
       for (int i = threadIdx.x; i < N / 2; i += 2 * kThreads) {
         const u64x2 a0 = pe[base + i], b0 = pz[base + i];
         const u64x2 a1 = pe[base + i + kThreads], b1 = pz[base + i + kThreads];
@@ -259,10 +288,18 @@ hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const u
 
 hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta,
                                const uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
-                               hipStream_t st) {
+                               const EncJob *bright, hipStream_t st) {
+  Bright br{nullptr, nullptr, 0, 0, 0.0, c->dev.cosj};
+  if (bright && bright->seg_b) {
+    br.seg_end = bright->seg_end;
+    br.seg_b = bright->seg_b;
+    br.n_seg = bright->n_seg;
+    br.seg_base = bright->seg_base;
+    br.scale = bright->bright_scale;
+  }
   // n is an upper bound of the hit count, which the kernel reads
   hipLaunchKernelGGL(k_value_gather, dim3(grid_for(n, 1)), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
-                     meta, hits, counters + 1, c->prm.L, c->prm.log_n, c->d_lc, out);
+                     meta, hits, counters + 1, c->prm.L, c->prm.log_n, c->d_lc, br, out);
   return hipGetLastError();
 }
 

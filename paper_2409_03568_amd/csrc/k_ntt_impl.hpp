@@ -6,6 +6,8 @@
 // per workgroup) and RC (reduction class of the primes, see ntt.hpp).  Each ring degree is
 // instantiated in its own translation unit (k_ntt_<LOGN>.hip).
 #pragma once
+#include <atomic>
+
 #include "internal.hpp"
 #include "ntt.hpp"
 #include "philox.hpp"
@@ -78,6 +80,8 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     const uint64_t item = job.list ? (uint64_t)job.list[it] : it;
     const uint64_t t = job.ts ? job.ts[item] : job.first_index + item;
     const double value = job.vals ? (double)job.vals[item] : (double)job.px[item];
+    const double fb = job.seg_b ? job.seg_b[segment_of(job.seg_end, job.n_seg, job.seg_base + item)] * job.bright_scale
+                                : 0.0;
     uint64_t *out = job.out + item * (uint64_t)(2 * L) * N;
     __syncthreads();
     uint32_t smp[R];
@@ -101,7 +105,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
         for (int r = 0; r < R; r++) {
           const int j = tid + T * r;
           double v = y[r] + (double)smp_g(smp[r], poly == 0 ? 8 : 16, B);
-          if (poly == 0) v += __builtin_rint(value * dt.enc_T[j]);
+          if (poly == 0) v += __builtin_rint(value * dt.enc_T[j]) + __builtin_rint(fb * dt.cosj[j]);
           __builtin_nontemporal_store((uint64_t)canon(v, q, qinv), dst + j);
         }
       }
@@ -262,37 +266,45 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 // ---------------------------------------------------------------------------
 // launch helpers for one ring degree
 // ---------------------------------------------------------------------------
-template <int LOGN, int LOGR, typename F>
-static hipError_t set_lds(F kernel) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)Shape<LOGN, LOGR>::lds_bytes);
+template <int LOGN, int LOGR, auto KERNEL>
+static hipError_t set_lds() {
+  // once per kernel and device (also keeps the call out of graph captures after the first launch)
+  static std::atomic<uint64_t> done{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 63;
+  const uint64_t bit = 1ull << dev;
+  if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(KERNEL),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Shape<LOGN, LOGR>::lds_bytes);
+  if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
 }
 
 template <int LOGN, int LOGR, int RC>
 struct Launch {
   using S = Shape<LOGN, LOGR>;
   static hipError_t encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
-    hipError_t e = set_lds<LOGN, LOGR>(k_encrypt<LOGN, LOGR, RC>);
+    hipError_t e = set_lds<LOGN, LOGR, k_encrypt<LOGN, LOGR, RC>>();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_encrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, job, c->d_lc,
                        c->dev);
     return hipGetLastError();
   }
   static hipError_t keygen(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
-    hipError_t e = set_lds<LOGN, LOGR>(k_keygen<LOGN, LOGR, RC>);
+    hipError_t e = set_lds<LOGN, LOGR, k_keygen<LOGN, LOGR, RC>>();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_keygen<LOGN, LOGR, RC>), dim3(c->lc.L), dim3(S::T), S::lds_bytes, st, s0, s1, c->d_lc, c->dev);
     return hipGetLastError();
   }
   static hipError_t prepare(const ckks_ctx *c, hipStream_t st) {
-    hipError_t e = set_lds<LOGN, LOGR>(k_keys_prepare<LOGN, LOGR, RC>);
+    hipError_t e = set_lds<LOGN, LOGR, k_keys_prepare<LOGN, LOGR, RC>>();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_keys_prepare<LOGN, LOGR, RC>), dim3(c->lc.L, 3), dim3(S::T), S::lds_bytes, st, c->d_lc, c->dev);
     return hipGetLastError();
   }
   static hipError_t decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
                             hipStream_t st) {
-    hipError_t e = set_lds<LOGN, LOGR>(k_decrypt<LOGN, LOGR, RC>);
+    hipError_t e = set_lds<LOGN, LOGR, k_decrypt<LOGN, LOGR, RC>>();
     if (e != hipSuccess) return e;
     const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
     hipLaunchKernelGGL((k_decrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, cts, n, level,
@@ -306,9 +318,9 @@ struct Launch {
 template <int LOGN>
 struct RingLaunch {
   template <typename F>
-  static hipError_t pick(const ckks_ctx *c, F f) {
-    if (c->logr == 4) return c->rc ? f(Launch<LOGN, 4, 1>{}) : f(Launch<LOGN, 4, 0>{});
-    if (c->logr == 5) return c->rc ? f(Launch<LOGN, 5, 1>{}) : f(Launch<LOGN, 5, 0>{});
+  static hipError_t pick(const ckks_ctx *c, int logr, F f) {
+    if (logr == 4) return c->rc ? f(Launch<LOGN, 4, 1>{}) : f(Launch<LOGN, 4, 0>{});
+    if (logr == 5) return c->rc ? f(Launch<LOGN, 5, 1>{}) : f(Launch<LOGN, 5, 0>{});
     return hipErrorInvalidValue;
   }
 };
@@ -319,16 +331,17 @@ struct RingLaunch {
 #define CKKS_DEFINE_RING_LAUNCHERS(LOGN)                                                                            \
   namespace ckks {                                                                                                  \
   hipError_t launch_encrypt_##LOGN(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {           \
-    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::encrypt(c, job, grid, st); });                \
+    return RingLaunch<LOGN>::pick(c, c->logr_enc, [&](auto L) { return decltype(L)::encrypt(c, job, grid, st); });  \
   }                                                                                                                 \
   hipError_t launch_keygen_##LOGN(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {                    \
-    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::keygen(c, s0, s1, st); });                    \
+    return RingLaunch<LOGN>::pick(c, c->logr_enc, [&](auto L) { return decltype(L)::keygen(c, s0, s1, st); });      \
   }                                                                                                                 \
   hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *c, hipStream_t st) {                                        \
-    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::prepare(c, st); });                           \
+    return RingLaunch<LOGN>::pick(c, c->logr_enc, [&](auto L) { return decltype(L)::prepare(c, st); });             \
   }                                                                                                                 \
   hipError_t launch_decrypt_##LOGN(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale,     \
                                    double *out, hipStream_t st) {                                                   \
-    return RingLaunch<LOGN>::pick(c, [&](auto L) { return decltype(L)::decrypt(c, cts, n, level, scale, out, st); }); \
+    return RingLaunch<LOGN>::pick(c, c->logr_dec,                                                                   \
+                                  [&](auto L) { return decltype(L)::decrypt(c, cts, n, level, scale, out, st); });  \
   }                                                                                                                 \
   }

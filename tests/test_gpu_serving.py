@@ -53,12 +53,11 @@ def _direct(P, ctx, cache, img, seed, k):
     import torch
 
     px = torch.from_numpy(img.reshape(-1)).cuda()
-    s = torch.cuda.Stream()
-    ct = ctx.encrypt_cached(cache, px, seed, stream=s) if cache is not None else ctx.encrypt_pixels(px, seed, stream=s)
+    ct = ctx.encrypt_cached(cache, px, seed) if cache is not None else ctx.encrypt_pixels(px, seed)
     if k:
-        ct = ctx.mean_filter(ct, img.shape[0], img.shape[1], k, stream=s)
-    out = ctx.decrypt_pixels(ct, stream=s)
-    s.synchronize()
+        ct = ctx.mean_filter(ct, img.shape[0], img.shape[1], k)
+    out = ctx.decrypt_pixels(ct)
+    torch.cuda.synchronize()
     return out.cpu().numpy().reshape(img.shape)
 
 
