@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--ntt-width", type=int, default=0, help="values per NTT thread (16 or 32; 0 = library default)")
     ap.add_argument("--batched-runs", type=int, default=2,
                     help="timed runs of the 64-image batched workload (0 = skip it)")
+    ap.add_argument("--pipeline-runs", type=int, default=5,
+                    help="timed runs per variant of the streamed 512x512 pipeline (0 = skip it)")
     ap.add_argument("--serving-jobs", type=int, default=200,
                     help="jobs per load point of the serving measurement (0 = skip it)")
     ap.add_argument("--serving-budget-gb", type=float, default=160.0, help="device bytes the server may hold")
@@ -152,6 +154,59 @@ def batched_bench(P, W, runs):
     cache.close()
     ctx.close()
     del d_px, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def pipeline_bench(P, W, runs):
+    """512x512 Zipf image at N=4096 / 3x36-bit: plain, radix and value-cache encryption ->
+    5x5 mean filter -> decryption, in tiles of 64 rows on three overlapped streams, against
+    the same tiles on one stream and against the whole image at once."""
+    import torch
+
+    cfg = 5
+    c = W.CONFIGS[cfg]
+    e = c.extras
+    img = W.config_image(cfg)
+    H, Wd = img.shape
+    n = img.size
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale, device=0)
+    ctx.keygen(W.keygen_seed(cfg))
+    px = torch.from_numpy(img.reshape(-1)).cuda()
+    caches = {"plain": None,
+              "radix": ctx.cache_build(P.CKKS_CACHE_RADIX, base=e["base"], digits=e["digits"], seed=W.cache_seed(cfg)),
+              "value": ctx.cache_build(P.CKKS_CACHE_VALUE_TOPK, topk=e["topk"], zero_pool=e["pool"], scan_px=px,
+                                       seed=W.cache_seed(cfg))}
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    R = e["k"] // 2
+    pad = np.pad(img.astype(np.float64), R, mode="edge")
+    box = sum(pad[dy:dy + H, dx:dx + Wd] for dy in range(e["k"]) for dx in range(e["k"])) / (e["k"] ** 2)
+    res = {"pixels": n, "k": e["k"], "tile_rows": 64, "ciphertext_GB": round(n * ctx.ct_bytes() / 1e9, 1)}
+    for name, cache in caches.items():
+        row = {}
+        for mode, tile, streams in (("overlap_3_streams", 64, 3), ("tiles_1_stream", 64, 1), ("whole_image", H, 1)):
+            ctx.image_pipeline(px, H, Wd, W.job_seed(cfg), e["k"], tile, streams, cache=cache, out=out,
+                               stream=stream)
+            stream.synchronize()
+            times = []
+            for _ in range(runs):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record(stream)
+                ctx.image_pipeline(px, H, Wd, W.job_seed(cfg), e["k"], tile, streams, cache=cache, out=out,
+                                   stream=stream)
+                ev[1].record(stream)
+                stream.synchronize()
+                times.append(ev[0].elapsed_time(ev[1]))
+            ms = float(np.median(times))
+            row[mode] = {"ms_median": round(ms, 2), "ms_min": round(min(times), 2), "px_per_s": round(n / (ms / 1e3))}
+        row["max_abs_err"] = float(np.max(np.abs(out.cpu().numpy().reshape(H, Wd) - box)))
+        res[name] = row
+    for cch in caches.values():
+        if cch is not None:
+            cch.close()
+    ctx.close()
+    del px, out
     torch.cuda.empty_cache()
     return res
 
@@ -368,6 +423,8 @@ def main():
     torch.cuda.empty_cache()
     if args.batched_runs > 0:
         out["batched"] = batched_bench(P, W, args.batched_runs)
+    if args.pipeline_runs > 0:
+        out["pipeline"] = pipeline_bench(P, W, args.pipeline_runs)
     if args.serving_jobs > 0:
         out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb)
     if args.cpu_sample > 0:

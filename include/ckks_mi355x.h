@@ -17,6 +17,9 @@
  *    caller pointer is kept after the enqueued work has completed.
  *  - Asynchrony: compute calls validate their arguments synchronously, then
  *    enqueue on `stream` (a hipStream_t; NULL = the null stream) and return.
+ *    Temporary device buffers of a call (cache metadata, tile buffers) are taken from
+ *    a stream-ordered memory pool owned by the context, on the call's stream; the pool
+ *    keeps freed memory for later calls and returns it when the context is destroyed.
  *    Calls on different streams may run concurrently once keys and caches exist;
  *    two calls writing the same buffer must be ordered by the caller.
  *  - Ciphertext layout (coefficient domain, canonical residues in [0, q_i)):
@@ -300,6 +303,32 @@ int ckks_batch_run(ckks_batch_plan *plan, const uint8_t *d_px, uint64_t n, const
 
 void ckks_batch_plan_destroy(ckks_batch_plan *plan);
 
+/* ---- streamed image pipeline ----
+ * Encrypts an H x W image (plain, or with a radix / value cache, Sec. 2.2.2 / Sec. 3.2),
+ * applies the k x k clamp-edge mean filter (Sec. 4.4.1) and decrypts, in tiles of
+ * tile_rows output rows, so that only a few tiles of ciphertexts exist at any time.
+ * Each tile encrypts its rows plus k/2 halo rows above and below again (the same
+ * ciphertexts as a whole-image encryption, since every ciphertext depends only on its
+ * pixel and global index).  With streams = 3, encryption, filtering and decryption run
+ * on three streams of the context with two buffers per stage, so tile t+1 is encrypted
+ * while tile t is filtered and tile t-1 decrypted; the caller's stream waits for all of
+ * it.  streams = 1 runs the tiles one after another on the caller's stream.  Results
+ * equal ckks_encrypt_* -> ckks_mean_filter -> ckks_decrypt_pixels on the whole image, bit
+ * for bit.  Tile buffers come from the context's scratch pool on the caller's stream.
+ * Calls on one context with streams = 3 must not overlap (they share the stage streams).
+ */
+typedef struct {
+  uint32_t tile_rows;  /* output rows per tile (>= 1) */
+  uint32_t streams;    /* 1 or 3 */
+  uint32_t filter_k;   /* 1, 3, 5 or 7 */
+  uint32_t reserved;
+} ckks_pipeline_config;
+
+/* d_px: H*W pixels; d_out: H*W doubles (decrypted filtered pixels); both device. */
+int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint32_t H, uint32_t W,
+                        const uint64_t seed[2], uint64_t first_index, const ckks_pipeline_config *cfg, double *d_out,
+                        void *stream);
+
 /* ---- serving runtime ----
  * A server runs whole image jobs -- encrypt every pixel (plain or cached, Sec. 2.2.2 /
  * Sec. 3.2), apply the k x k mean filter (Sec. 4.4.1), decrypt (Sec. 2.2.2) -- for
@@ -311,7 +340,7 @@ void ckks_batch_plan_destroy(ckks_batch_plan *plan);
  * Job bytes = align(n) + n*S(L) + n*S(L-1) + align(8n) for n = H*W pixels and
  * S(l) = ckks_ct_bytes(ctx, l) (pixels, ciphertexts, filtered ciphertexts, decrypted
  * values); cached encryption also takes its small per-pixel metadata (12 bytes per pixel)
- * from the stream-ordered pool.  A job's results do not depend on which other jobs run
+ * from the context's scratch pool.  A job's results do not depend on which other jobs run
  * beside it: its ciphertexts are fixed by (job_seed, first_index) and every kernel's
  * result is independent of the launch that computes it.
  */

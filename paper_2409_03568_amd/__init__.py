@@ -71,6 +71,11 @@ class ckks_tune_report_t(C.Structure):
                 ("reserved", C.c_uint32), ("encrypt_ms", C.c_double * 2), ("decrypt_ms", C.c_double * 2)]
 
 
+class ckks_pipeline_config_t(C.Structure):
+    _fields_ = [("tile_rows", C.c_uint32), ("streams", C.c_uint32), ("filter_k", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
 class ckks_batch_config_t(C.Structure):
     _fields_ = [("chunk_cts", C.c_uint64), ("use_graph", C.c_uint32), ("reserved", C.c_uint32)]
 
@@ -114,6 +119,9 @@ _SIGS = {
                                    C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_decrypt_pixels": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_void_p, C.c_void_p]),
     "ckks_stream_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ckks_image_pipeline": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
+                                      C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(ckks_pipeline_config_t),
+                                      C.c_void_p, C.c_void_p]),
     "ckks_autotune": (C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(ckks_tune_report_t)]),
     "ckks_batch_plan_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ckks_batch_config_t),
                                          C.POINTER(C.c_void_p)]),
@@ -392,6 +400,18 @@ class Context:
 
     def stream_sync(self, stream=None):
         _check(lib().ckks_stream_sync(self.handle, _stream(stream)))
+
+    def image_pipeline(self, px, H: int, W: int, seed, k: int, tile_rows: int, streams: int = 3,
+                       cache: "Cache | None" = None, first_index: int = 0, out=None, stream=None):
+        """Encrypt -> k x k mean filter -> decrypt of an H x W image in row tiles; returns the
+        decrypted filtered pixels (H*W doubles on the device)."""
+        import torch
+
+        out = torch.empty(H * W, dtype=torch.float64, device=px.device) if out is None else out
+        cfg = ckks_pipeline_config_t(int(tile_rows), int(streams), int(k), 0)
+        _check(lib().ckks_image_pipeline(self.handle, cache.handle if cache is not None else None, _ptr(px), H, W,
+                                         _seed(seed), int(first_index), C.byref(cfg), _ptr(out), _stream(stream)))
+        return out
 
     def autotune(self, trial_cts: int = 4096) -> dict:
         """Time both NTT register blockings for encryption and decryption; keep the faster."""

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libckks_mi355x.so")
 SOURCES = ["api.cpp", "host_math.cpp", "k_ntt_dispatch.cpp", "k_ntt_11.hip", "k_ntt_12.hip", "k_ntt_13.hip",
-           "k_ntt_14.hip", "k_ops.hip", "k_cache.hip", "server.cpp", "batch.cpp"]
+           "k_ntt_14.hip", "k_ops.hip", "k_cache.hip", "server.cpp", "batch.cpp", "pipeline.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -130,6 +130,49 @@ int const_multiplier(const ckks_ctx *c, uint32_t level, double scale, double cst
 }  // namespace
 
 namespace ckks {
+
+static uint64_t ws_align(uint64_t x) { return (x + 255) / 256 * 256; }
+
+uint64_t cached_ws_bytes(const ckks_cache *cache, uint64_t n) {
+  if (cache->kind == CKKS_CACHE_RADIX) return ws_align(n * kMaxDigits * sizeof(int16_t)) + 256;
+  return 3 * ws_align(n * sizeof(uint32_t)) + ws_align((2 + (uint64_t)cache->pool) * sizeof(uint32_t));
+}
+
+hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *px, uint64_t n,
+                             uint64_t seed0, uint64_t seed1, uint64_t first_index, uint64_t *out, void *ws,
+                             hipStream_t st) {
+  uint8_t *w = static_cast<uint8_t *>(ws);
+  if (cache->kind == CKKS_CACHE_RADIX) {
+    int16_t *meta = reinterpret_cast<int16_t *>(w);
+    uint32_t *bad = reinterpret_cast<uint32_t *>(w + ws_align(n * kMaxDigits * sizeof(int16_t)));
+    hipError_t e = launch_radix_meta(ctx, cache, px, n, first_index, seed0, seed1, meta, bad, st);
+    return e == hipSuccess ? launch_radix_gather(ctx, cache, meta, n, out, st) : e;
+  }
+  const uint64_t a = ws_align(n * sizeof(uint32_t));
+  uint32_t *meta = reinterpret_cast<uint32_t *>(w);
+  uint32_t *miss = reinterpret_cast<uint32_t *>(w + a);
+  uint32_t *hits = reinterpret_cast<uint32_t *>(w + 2 * a);
+  uint32_t *counters = reinterpret_cast<uint32_t *>(w + 3 * a);
+  hipError_t e = launch_value_meta(ctx, cache, px, n, first_index, seed0, seed1, meta, miss, counters, hits, st);
+  if (e == hipSuccess) e = launch_value_gather(ctx, cache, meta, counters, hits, n, out, nullptr, st);
+  if (e != hipSuccess) return e;
+  EncJob job;
+  job.px = px;
+  job.list = miss;
+  job.list_count = counters;
+  job.n = n;
+  job.first_index = first_index;
+  job.seed0 = seed0;
+  job.seed1 = seed1;
+  job.out = out;
+  return launch_encrypt(ctx, job, std::min<uint64_t>(n, kListGrid), st);
+}
+
+int filter_multiplier(const ckks_ctx *c, uint32_t level, double scale, uint32_t k, std::vector<uint64_t> &K,
+                      double *new_scale) {
+  return const_multiplier(c, level, scale, 1.0 / (double)(k * k), K, new_scale, true);
+}
+
 int api_fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -239,6 +282,18 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   if (e == hipSuccess) e = upload(d.cdt, host::cdt_table(r.sigma, r.B, kCdtSlots));
   if (e == hipSuccess) e = dev_alloc(&c->d_lc, 1);
   if (e == hipSuccess) e = hipMemcpy(c->d_lc, &c->lc, sizeof(LimbConsts), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    // scratch pool of the context: per-call workspaces come from it on the call's
+    // stream; memory freed into it is kept for the next call instead of being unmapped
+    // at every synchronization (the default pool's behaviour)
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    e = hipMemPoolCreate(&c->pool, &props);
+    uint64_t keep = ~0ull;
+    if (e == hipSuccess) e = hipMemPoolSetAttribute(c->pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   if (e != hipSuccess) {
     free_tables(c);
     delete c;
@@ -252,7 +307,10 @@ void ckks_context_destroy(ckks_ctx *ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
+  for (hipStream_t &st : ctx->pipe)
+    if (st) (void)hipStreamDestroy(st);
   free_tables(ctx);
+  if (ctx->pool) (void)hipMemPoolDestroy(ctx->pool);
   delete ctx;
 }
 
@@ -436,7 +494,7 @@ int ckks_cache_build(ckks_ctx *ctx, const ckks_cache_desc *desc, const uint8_t *
   }
   uint32_t *hist = nullptr;
   if (kind == CKKS_CACHE_VALUE_TOPK) {
-    e = hipMallocAsync(reinterpret_cast<void **>(&hist), 256 * sizeof(uint32_t), st);
+    e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&hist), 256 * sizeof(uint32_t), ctx->pool, st);
     if (e == hipSuccess) e = launch_histogram_topk(ctx, d_scan, n_scan, desc->topk, hist, c, st);
     if (e == hipSuccess) e = hipFreeAsync(hist, st);
   }
@@ -532,40 +590,10 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
   if (n == 0) return CKKS_OK;
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  if (cache->kind == CKKS_CACHE_RADIX) {
-    int16_t *meta = nullptr;
-    uint32_t *bad = nullptr;
-    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&meta), n * kMaxDigits * sizeof(int16_t), st), "meta alloc");
-    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&bad), sizeof(uint32_t), st), "flag alloc");
-    HIP_TRY(launch_radix_meta(ctx, cache, d_px, n, first_index, seed[0], seed[1], meta, bad, st), "radix meta");
-    HIP_TRY(launch_radix_gather(ctx, cache, meta, n, out->data, st), "radix gather");
-    HIP_TRY(hipFreeAsync(meta, st), "meta free");
-    HIP_TRY(hipFreeAsync(bad, st), "flag free");
-    return CKKS_OK;
-  }
-  uint32_t *meta = nullptr, *miss = nullptr, *hits = nullptr, *counters = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&meta), n * sizeof(uint32_t), st), "meta alloc");
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&miss), n * sizeof(uint32_t), st), "miss list alloc");
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&hits), n * sizeof(uint32_t), st), "hit list alloc");
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&counters), (2 + (size_t)cache->pool) * sizeof(uint32_t), st),
-          "counter alloc");
-  HIP_TRY(launch_value_meta(ctx, cache, d_px, n, first_index, seed[0], seed[1], meta, miss, counters, hits, st),
-          "value meta");
-  HIP_TRY(launch_value_gather(ctx, cache, meta, counters, hits, n, out->data, nullptr, st), "value gather");
-  EncJob job;
-  job.px = d_px;
-  job.list = miss;
-  job.list_count = counters;
-  job.n = n;
-  job.first_index = first_index;
-  job.seed0 = seed[0];
-  job.seed1 = seed[1];
-  job.out = out->data;
-  HIP_TRY(launch_encrypt(ctx, job, std::min<uint64_t>(n, kListGrid), st), "miss encryption");
-  HIP_TRY(hipFreeAsync(meta, st), "meta free");
-  HIP_TRY(hipFreeAsync(miss, st), "miss list free");
-  HIP_TRY(hipFreeAsync(hits, st), "hit list free");
-  HIP_TRY(hipFreeAsync(counters, st), "counter free");
+  void *ws = nullptr;
+  HIP_TRY(hipMallocFromPoolAsync(&ws, cached_ws_bytes(cache, n), ctx->pool, st), "workspace alloc");
+  HIP_TRY(encrypt_cached_ws(ctx, cache, d_px, n, seed[0], seed[1], first_index, out->data, ws, st), "cached encryption");
+  HIP_TRY(hipFreeAsync(ws, st), "workspace free");
   return CKKS_OK;
 }
 
@@ -675,7 +703,8 @@ int ckks_mean_filter(ckks_ctx *ctx, const ckks_ct_batch *img, uint32_t H, uint32
   out->scale = s1 / (double)ctx->prm.q[iv.level - 1];
   if (!iv.count) return CKKS_OK;
   DeviceGuard g(ctx->device);
-  HIP_TRY(launch_mean_filter(ctx, iv.data, out->data, H, W, k, (int)iv.level, K.data(), as_stream(stream)), "mean filter");
+  HIP_TRY(launch_mean_filter(ctx, iv.data, out->data, H, W, 0, H, k, (int)iv.level, K.data(), as_stream(stream)),
+          "mean filter");
   return CKKS_OK;
 }
 

@@ -90,6 +90,8 @@ struct ckks_ctx {
   ckks::DevTables dev{};
   std::vector<uint64_t> ninv;  // N^-1 mod q_i
   bool has_keys = false;
+  hipStream_t pipe[3] = {nullptr, nullptr, nullptr};  // image pipeline stages, created on first use
+  hipMemPool_t pool = nullptr;  // stream-ordered scratch that keeps its memory between calls
 };
 
 struct ckks_cache {
@@ -111,6 +113,18 @@ namespace ckks {
 // Records a message for ckks_last_error() (thread-local) and returns `code`.
 int api_fail(int code, const char *fmt, ...);
 
+// Mean-filter multiplier: 1/k^2 as rint(q_{level-1} / k^2) per limb, and the scale after it.
+int filter_multiplier(const ckks_ctx *c, uint32_t level, double scale, uint32_t k, std::vector<uint64_t> &K,
+                      double *new_scale);
+
+// Cached encryption of n pixels with caller-provided scratch (cached_ws_bytes(cache, n)
+// bytes of device memory, 256-byte aligned): value caches gather hits and plain-encrypt
+// misses, radix caches combine their entries.
+uint64_t cached_ws_bytes(const ckks_cache *cache, uint64_t n);
+hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *px, uint64_t n,
+                             uint64_t seed0, uint64_t seed1, uint64_t first_index, uint64_t *out, void *ws,
+                             hipStream_t stream);
+
 // Launchers (return a hipError_t; enqueue on `stream`).
 hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
 hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream);
@@ -126,8 +140,10 @@ hipError_t launch_add_const(const ckks_ctx *c, uint64_t *a, uint64_t n, int leve
                             double b, hipStream_t stream);
 hipError_t launch_rescale(const ckks_ctx *c, const uint64_t *a, uint64_t *out, uint64_t n, int level,
                           hipStream_t stream);
+// k x k mean filter of an H x W image of ciphertexts, output rows [y0, y1) (out holds
+// y1 - y0 rows); K = the per-limb multiplier rint(q_last / k^2) mod q_i.
 hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
-                              uint32_t k, int level, const uint64_t *K, hipStream_t stream);
+                              uint32_t y0, uint32_t y1, uint32_t k, int level, const uint64_t *K, hipStream_t stream);
 
 hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t n, uint32_t topk, uint32_t *hist,
                                  ckks_cache *cache, hipStream_t stream);

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kRowThreads)
 
 // Fused k x k mean filter with clamped borders: out(y,x) = rescale(K * sum of the window).
 // Thread (x-tile, poly, j) owns XT adjacent output columns of coefficient j and walks down
-// the image, keeping the horizontal window sums of the last k rows in a ring; the
+// output rows y_begin..y_end-1 of the image (written as rows 0.. of out), keeping the horizontal window sums of the last k rows in a ring; the
 // vertical sum is updated by adding the row that enters and subtracting the row that
 // leaves.  Arithmetic is exact FP64 on signed representatives:
 //   a horizontal sum of k <= 7 canonical residues is below 7q < 2^53 and is reduced to
@@ -135,8 +135,8 @@ constexpr int kFilterWaves = kRowThreads / 64;
 
 template <int KW, int LV, int XT>
 __global__ void __launch_bounds__(kRowThreads)
-    k_mean_filter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t H, uint32_t W, int log_n,
-                  uint32_t groups, FilterConsts fc) {
+    k_mean_filter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t H, uint32_t W, uint32_t y_begin,
+                  uint32_t y_end, int log_n, uint32_t groups, FilterConsts fc) {
   constexpr int RAD = KW / 2, XC = XT + 2 * RAD;
   const int N = 1 << log_n;
   // logical workgroup lb = (64-coefficient chunk jc, poly, tile group g), g fastest; its
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kRowThreads)
     for (int i = 0; i < LV; i++) v[t][i] = 0.0;
 #pragma unroll
   for (int d = 0; d < KW; d++) {
-    hsum((int64_t)d - RAD, ring[d]);
+    hsum((int64_t)y_begin + d - RAD, ring[d]);
 #pragma unroll
     for (int t = 0; t < XT; t++)
 #pragma unroll
@@ -196,16 +196,16 @@ __global__ void __launch_bounds__(kRowThreads)
   const uint64_t out_stride = (uint64_t)2 * (LV - 1) * N;
   const uint64_t out_base = (uint64_t)poly * (LV - 1) * N + j;
   const double ql = fc.q[LV - 1], qlinv = fc.qinv[LV - 1];
-  for (uint32_t y0 = 0; y0 < H; y0 += KW) {
+  for (uint32_t y0 = y_begin; y0 < y_end; y0 += KW) {
 #pragma unroll
     for (int s = 0; s < KW; s++) {
       const uint32_t y = y0 + s;
-      if (y >= H) break;
+      if (y >= y_end) break;
 #pragma unroll
       for (int t = 0; t < XT; t++) {
         if (x0 + t >= W) break;
         const double r = canon(mulmod(v[t][LV - 1], fc.K[LV - 1], ql, qlinv) + fc.h, ql, qlinv);
-        uint64_t *o = out + ((uint64_t)y * W + x0 + t) * out_stride + out_base;
+        uint64_t *o = out + ((uint64_t)(y - y_begin) * W + x0 + t) * out_stride + out_base;
 #pragma unroll
         for (int i = 0; i < LV - 1; i++) {
           const double m = mulmod(v[t][i], fc.K[i], fc.q[i], fc.qinv[i]);
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kRowThreads)
         }
       }
       // slide the window: ring slot s holds row y - RAD; replace it by row y + RAD + 1
-      if (y + 1 < H) {
+      if (y + 1 < y_end) {
         double nh[XT][LV];
         hsum((int64_t)y + RAD + 1, nh);
 #pragma unroll
@@ -300,29 +300,29 @@ constexpr int filter_xt() {
 }
 
 template <int KW, int LV>
-static hipError_t filter_t(const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, int log_n,
-                           const FilterConsts &fc, hipStream_t st) {
+static hipError_t filter_t(const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, uint32_t y0, uint32_t y1,
+                           int log_n, const FilterConsts &fc, hipStream_t st) {
   constexpr int XT = filter_xt<KW, LV>();
   const uint64_t tiles = ((uint64_t)W + XT - 1) / XT;
   const uint64_t groups = (tiles + kFilterWaves - 1) / kFilterWaves;
   const uint64_t blocks = groups * 2 * (((uint64_t)1 << log_n) / 64);
   if (blocks > 0xffffffffull) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_mean_filter<KW, LV, XT>), dim3((uint32_t)blocks), dim3(kRowThreads), 0, st, in, out, H, W,
-                     log_n, (uint32_t)groups, fc);
+                     y0, y1, log_n, (uint32_t)groups, fc);
   return hipGetLastError();
 }
 
 template <int KW>
-static hipError_t filter_level(int level, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, int log_n,
-                               const FilterConsts &fc, hipStream_t st) {
+static hipError_t filter_level(int level, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, uint32_t y0,
+                               uint32_t y1, int log_n, const FilterConsts &fc, hipStream_t st) {
   switch (level) {
-    case 2: return filter_t<KW, 2>(in, out, H, W, log_n, fc, st);
-    case 3: return filter_t<KW, 3>(in, out, H, W, log_n, fc, st);
-    case 4: return filter_t<KW, 4>(in, out, H, W, log_n, fc, st);
-    case 5: return filter_t<KW, 5>(in, out, H, W, log_n, fc, st);
-    case 6: return filter_t<KW, 6>(in, out, H, W, log_n, fc, st);
-    case 7: return filter_t<KW, 7>(in, out, H, W, log_n, fc, st);
-    case 8: return filter_t<KW, 8>(in, out, H, W, log_n, fc, st);
+    case 2: return filter_t<KW, 2>(in, out, H, W, y0, y1, log_n, fc, st);
+    case 3: return filter_t<KW, 3>(in, out, H, W, y0, y1, log_n, fc, st);
+    case 4: return filter_t<KW, 4>(in, out, H, W, y0, y1, log_n, fc, st);
+    case 5: return filter_t<KW, 5>(in, out, H, W, y0, y1, log_n, fc, st);
+    case 6: return filter_t<KW, 6>(in, out, H, W, y0, y1, log_n, fc, st);
+    case 7: return filter_t<KW, 7>(in, out, H, W, y0, y1, log_n, fc, st);
+    case 8: return filter_t<KW, 8>(in, out, H, W, y0, y1, log_n, fc, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -332,7 +332,7 @@ static double centered_double(uint64_t x, uint64_t q) {
 }
 
 hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
-                              uint32_t k, int level, const uint64_t *K, hipStream_t st) {
+                              uint32_t y0, uint32_t y1, uint32_t k, int level, const uint64_t *K, hipStream_t st) {
   FilterConsts fc{};
   const uint64_t qlast = c->prm.q[(size_t)level - 1];
   for (int i = 0; i < level; i++) {
@@ -345,10 +345,10 @@ hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *o
   fc.h = (double)(qlast / 2);
   const int log_n = c->prm.log_n;
   switch (k) {
-    case 1: return filter_level<1>(level, in, out, H, W, log_n, fc, st);
-    case 3: return filter_level<3>(level, in, out, H, W, log_n, fc, st);
-    case 5: return filter_level<5>(level, in, out, H, W, log_n, fc, st);
-    case 7: return filter_level<7>(level, in, out, H, W, log_n, fc, st);
+    case 1: return filter_level<1>(level, in, out, H, W, y0, y1, log_n, fc, st);
+    case 3: return filter_level<3>(level, in, out, H, W, y0, y1, log_n, fc, st);
+    case 5: return filter_level<5>(level, in, out, H, W, y0, y1, log_n, fc, st);
+    case 7: return filter_level<7>(level, in, out, H, W, y0, y1, log_n, fc, st);
     default: return hipErrorInvalidValue;
   }
 }
