@@ -39,9 +39,11 @@ struct DevTables {
   double *s_hat = nullptr;   // [L][N] NTT domain times N^-1, centered
 };
 
-// What to encrypt: item i has value vals[i] (or px[i]) and Philox index ts[i]
-// (or first_index + i).  With list_count, *list_count items are encrypted: items
-// list[0..*list_count) if `list` is set, else items 0..*list_count-1; without it, 0..n-1.
+// What to encrypt, in one of three forms (the launcher picks the kernel variant):
+//   pixels:  items 0..n-1 with value px[i] and Philox index first_index + i;
+//   list:    items list[0..*list_count) with value px[item], index first_index + item;
+//   entries: items 0..count-1 (count = *list_count if set, else n) with value vals[i],
+//            index ts[i].
 struct EncJob {
   const uint8_t *px = nullptr;
   const uint32_t *vals = nullptr;

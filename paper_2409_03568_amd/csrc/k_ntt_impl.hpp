@@ -21,16 +21,21 @@ struct Shape : NttShape<LOGN, LOGR> {
   // table, and a reduction area
   static constexpr int SLOTS = LdsSlots<LOGN, LOGR>::value;
   static constexpr size_t lds_bytes = sizeof(double) * ((size_t)SLOTS + kCdtSlots + 64);
+  // Encryption also keeps the packed samples of the current ciphertext (4 bytes per
+  // coefficient) in LDS after the above when that fits a CU's 160 KiB, instead of in
+  // registers for the whole ciphertext.
+  static constexpr size_t smp_bytes = sizeof(uint32_t) * ((size_t)1 << LOGN);
+  static constexpr bool kSmpLds = lds_bytes + smp_bytes <= 160 * 1024;
+  static constexpr size_t enc_lds_bytes = lds_bytes + (kSmpLds ? smp_bytes : 0);
 };
 
-// Draw the packed samples of one polynomial triple into LDS and read them back in
-// the first-pass layout: smp[r] holds coefficient tid + T*r as
-// (t1 + 1) | (g2 + B) << 8 | (g3 + B) << 16, where t1 is the ternary value of stream
-// tag1 and g2, g3 the Gaussian values of streams tag2, tag3 (all at Philox index t).
+// Draw the packed samples of one polynomial triple into LDS: word j of dst holds
+// coefficient j as (t1 + 1) | (g2 + B) << 8 | (g3 + B) << 16, where t1 is the ternary
+// value of stream tag1 and g2, g3 the Gaussian values of streams tag2, tag3 (all at
+// Philox index t).  Each thread draws whole Philox blocks; ends with a barrier.
 template <int LOGN, int LOGR>
-__device__ __forceinline__ void draw_samples(uint32_t (&smp)[1 << LOGR], uint32_t *lds32, const uint64_t *cdt,
-                                             int B, int tid, uint64_t k0, uint64_t k1, uint64_t t, uint32_t tag1,
-                                             uint32_t tag2, uint32_t tag3) {
+__device__ __forceinline__ void draw_samples(uint32_t *dst, const uint64_t *cdt, int B, int tid, uint64_t k0,
+                                             uint64_t k1, uint64_t t, uint32_t tag1, uint32_t tag2, uint32_t tag3) {
   using S = NttShape<LOGN, LOGR>;
   static_assert(S::R >= 4, "each thread draws whole Philox blocks");
 #pragma unroll 1
@@ -48,9 +53,18 @@ __device__ __forceinline__ void draw_samples(uint32_t (&smp)[1 << LOGR], uint32_
       const uint32_t gb = (uint32_t)(gauss_of(pb.w[w], cdt, B) + B);
       pw[w] = tv | (ga << 8) | (gb << 16);
     }
-    reinterpret_cast<uint4 *>(lds32)[b] = packed;
+    reinterpret_cast<uint4 *>(dst)[b] = packed;
   }
   __syncthreads();
+}
+
+// The same, read back in the first-pass layout: smp[r] holds coefficient tid + T*r.
+template <int LOGN, int LOGR>
+__device__ __forceinline__ void draw_samples(uint32_t (&smp)[1 << LOGR], uint32_t *lds32, const uint64_t *cdt,
+                                             int B, int tid, uint64_t k0, uint64_t k1, uint64_t t, uint32_t tag1,
+                                             uint32_t tag2, uint32_t tag3) {
+  using S = NttShape<LOGN, LOGR>;
+  draw_samples<LOGN, LOGR>(lds32, cdt, B, tid, k0, k1, t, tag1, tag2, tag3);
 #pragma unroll
   for (int r = 0; r < S::R; r++) smp[r] = lds32[tid + S::T * r];
 }
@@ -62,7 +76,16 @@ __device__ __forceinline__ int smp_g(uint32_t s, int shift, int B) { return (int
 // fused plain encryption: per ciphertext, per limb
 //   x = NTT(v); c0 = INTT(x * pk0^) + e0 + m; c1 = INTT(x * pk1^) + e1
 // ---------------------------------------------------------------------------
-template <int LOGN, int LOGR, int RC>
+// Where item i's pixel value and Philox index come from (compiled separately, so each
+// variant keeps only the pointers it reads live):
+//   kEncPixels:  items 0..n-1, value px[i], index first_index + i;
+//   kEncList:    items list[0..*list_count), value px[item], index first_index + item;
+//   kEncEntries: items 0..count-1 (count = *list_count if set, else n), value vals[i],
+//                index ts[i].
+// BRIGHT adds the image's brightness encoding to c0 (EncJob::seg_b).
+enum EncMode : int { kEncPixels = 0, kEncList = 1, kEncEntries = 2 };
+
+template <int LOGN, int LOGR, int RC, int MODE, bool BRIGHT>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     k_encrypt(EncJob job, const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
@@ -72,26 +95,37 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   extern __shared__ double lds[];
   uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
   uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
+  uint32_t *smpl = reinterpret_cast<uint32_t *>(lds + S::SLOTS + kCdtSlots + 64);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
   const int L = lc.L, B = lc.B;
-  const uint64_t count = job.list_count ? (uint64_t)*job.list_count : job.n;
+  uint64_t count = job.n;
+  if (MODE == kEncList || (MODE == kEncEntries && job.list_count)) count = *job.list_count;
   for (uint64_t it = blockIdx.x; it < count; it += gridDim.x) {
-    const uint64_t item = job.list ? (uint64_t)job.list[it] : it;
-    const uint64_t t = job.ts ? job.ts[item] : job.first_index + item;
-    const double value = job.vals ? (double)job.vals[item] : (double)job.px[item];
-    const double fb = job.seg_b ? job.seg_b[segment_of(job.seg_end, job.n_seg, job.seg_base + item)] * job.bright_scale
-                                : 0.0;
+    const uint64_t item = MODE == kEncList ? (uint64_t)job.list[it] : it;
+    const uint64_t t = MODE == kEncEntries ? job.ts[item] : job.first_index + item;
+    const double value = MODE == kEncEntries ? (double)job.vals[item] : (double)job.px[item];
+    const double fb =
+        BRIGHT ? job.seg_b[segment_of(job.seg_end, job.n_seg, job.seg_base + item)] * job.bright_scale : 0.0;
     uint64_t *out = job.out + item * (uint64_t)(2 * L) * N;
     __syncthreads();
-    uint32_t smp[R];
-    draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
+    uint32_t smp[R];  // used when the samples stay in registers
+    if constexpr (S::kSmpLds)
+      draw_samples<LOGN, LOGR>(smpl, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
+    else
+      draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
     for (int l = 0; l < L; l++) {
       const double q = lc.q[l], qinv = lc.qinv[l];
       const int tid = opaque(threadIdx.x);
+      auto sample = [&](int r) -> uint32_t {
+        if constexpr (S::kSmpLds)
+          return smpl[tid + T * r];
+        else
+          return smp[r];
+      };
       double x[R];
 #pragma unroll
-      for (int r = 0; r < R; r++) x[r] = (double)smp_t(smp[r]);
+      for (int r = 0; r < R; r++) x[r] = (double)smp_t(sample(r));
       ntt_forward<LOGN, LOGR, Red::fwd_small>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
 #pragma unroll 1
       for (int poly = 0; poly < 2; poly++) {
@@ -104,8 +138,11 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 #pragma unroll
         for (int r = 0; r < R; r++) {
           const int j = tid + T * r;
-          double v = y[r] + (double)smp_g(smp[r], poly == 0 ? 8 : 16, B);
-          if (poly == 0) v += __builtin_rint(value * dt.enc_T[j]) + __builtin_rint(fb * dt.cosj[j]);
+          double v = y[r] + (double)smp_g(sample(r), poly == 0 ? 8 : 16, B);
+          if (poly == 0) {
+            v += __builtin_rint(value * dt.enc_T[j]);
+            if (BRIGHT) v += __builtin_rint(fb * dt.cosj[j]);
+          }
           __builtin_nontemporal_store((uint64_t)canon(v, q, qinv), dst + j);
         }
       }
@@ -266,7 +303,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 // ---------------------------------------------------------------------------
 // launch helpers for one ring degree
 // ---------------------------------------------------------------------------
-template <int LOGN, int LOGR, auto KERNEL>
+template <int LOGN, int LOGR, auto KERNEL, size_t BYTES = Shape<LOGN, LOGR>::lds_bytes>
 static hipError_t set_lds() {
   // once per kernel and device (also keeps the call out of graph captures after the first launch)
   static std::atomic<uint64_t> done{0};
@@ -275,7 +312,7 @@ static hipError_t set_lds() {
   const uint64_t bit = 1ull << dev;
   if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
   const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(KERNEL),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Shape<LOGN, LOGR>::lds_bytes);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)BYTES);
   if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
   return e;
 }
@@ -283,12 +320,26 @@ static hipError_t set_lds() {
 template <int LOGN, int LOGR, int RC>
 struct Launch {
   using S = Shape<LOGN, LOGR>;
-  static hipError_t encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
-    hipError_t e = set_lds<LOGN, LOGR, k_encrypt<LOGN, LOGR, RC>>();
+  template <int MODE, bool BRIGHT>
+  static hipError_t encrypt_as(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR, k_encrypt<LOGN, LOGR, RC, MODE, BRIGHT>, S::enc_lds_bytes>();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_encrypt<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, job, c->d_lc,
-                       c->dev);
+    hipLaunchKernelGGL((k_encrypt<LOGN, LOGR, RC, MODE, BRIGHT>), dim3((uint32_t)grid), dim3(S::T), S::enc_lds_bytes,
+                       st, job, c->d_lc, c->dev);
     return hipGetLastError();
+  }
+  static hipError_t encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {
+    const bool bright = job.seg_b != nullptr;
+    if (job.vals || job.ts) {
+      if (!job.vals || !job.ts || bright) return hipErrorInvalidValue;
+      return encrypt_as<kEncEntries, false>(c, job, grid, st);
+    }
+    if (job.list) {
+      if (!job.list_count) return hipErrorInvalidValue;
+      return bright ? encrypt_as<kEncList, true>(c, job, grid, st) : encrypt_as<kEncList, false>(c, job, grid, st);
+    }
+    if (job.list_count) return hipErrorInvalidValue;
+    return bright ? encrypt_as<kEncPixels, true>(c, job, grid, st) : encrypt_as<kEncPixels, false>(c, job, grid, st);
   }
   static hipError_t keygen(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
     hipError_t e = set_lds<LOGN, LOGR, k_keygen<LOGN, LOGR, RC>>();

@@ -19,8 +19,9 @@
 // Lazy reduction: values are signed and grow through the stages; a reduction after
 // stage s is compiled in when bit s of the schedule is set.  The schedules are fixed at
 // compile time per reduction class (class 0: primes small enough to need none; class 1:
-// primes below 2^50), derived from worst-case magnitude bounds so that every value stays
-// below 2^51 (see modarith.hpp for the bounds of the primitive operations).
+// primes below 2^50), derived from worst-case magnitude bounds so that forward values
+// stay below 2^52 and inverse values below 2^51 (see modarith.hpp for the bounds of the
+// primitive operations).
 #pragma once
 #include "modarith.hpp"
 
@@ -43,20 +44,30 @@ struct NttShape {
 // reduce(x): |r| <= q/2 + 1.  A stage is followed by a reduction when its outputs could
 // exceed 2^51.  The bounds grow with q, so a schedule derived for qmax serves every
 // smaller prime.
-constexpr double kBoundLimit = 2251799813685248.0;   // 2^51
+// Forward (Cooley-Tukey) stages add a product to a value: X +- W*Y.  The product
+// precondition |Y W / q| < 2^51 holds for |Y| below 2^52 (|W| <= q/2), so forward values
+// may grow to just under 2^52.  Inverse (Gentleman-Sande) stages form X - Y before the
+// product, so their values are kept below 2^51 (the difference then stays below 2^52).
+constexpr double kFwdLimit = 4222124650659840.0;  // 2^52 - 2^48
+constexpr double kInvLimit = 2251799813685248.0;  // 2^51
 constexpr double kTwoPowMinus53 = 1.0 / 9007199254740992.0;
 
-constexpr uint32_t forward_schedule(int log_n, double qmax, double input_bound) {
+struct FwdPlan {
+  uint32_t mask;  // reduce after stage s when bit s is set
+  double bound;   // bound on the outputs
+};
+
+constexpr FwdPlan forward_schedule(int log_n, double qmax, double input_bound) {
   uint32_t mask = 0;
   double M = input_bound;
   for (int s = 0; s < log_n; s++) {
     M = M + (qmax / 2 + M * qmax * kTwoPowMinus53 + 1);
-    if (M > kBoundLimit) {
+    if (M > kFwdLimit) {
       mask |= 1u << s;
       M = qmax / 2 + 2;
     }
   }
-  return mask;
+  return FwdPlan{mask, M};
 }
 
 // Inverse: the sum output doubles, the difference output goes through a product; only
@@ -67,7 +78,7 @@ constexpr uint32_t inverse_schedule(int log_n, double qmax, double input_bound) 
   for (int s = log_n - 1; s >= 0; s--) {
     const double prod = qmax / 2 + 2 * M * qmax * kTwoPowMinus53 + 1;
     double sum = 2 * M;
-    if (sum > kBoundLimit) {
+    if (sum > kInvLimit) {
       mask |= 1u << s;
       sum = qmax / 2 + 2;
     }
@@ -76,16 +87,24 @@ constexpr uint32_t inverse_schedule(int log_n, double qmax, double input_bound) 
   return mask;
 }
 
-// Inputs of the transforms: small signed values (ternary, |x| <= 1), canonical residues
-// (< q), and pointwise products of a value below 2^51 with a reduced key (<= 3q/4 + 2).
+// Pointwise product of a forward output (bound M) with a reduced key (|w| <= q/2 + 2).
+constexpr double pointwise_bound(double qmax, double M) { return qmax / 2 + M * (qmax / 2 + 2) * 2 * kTwoPowMinus53 + 1; }
+
+// Inputs of the transforms: small signed values (ternary, |x| <= 1) or canonical
+// residues (< q); the inverse starts from pointwise products of either's output.
 constexpr double kClassQmax[2] = {1099511627776.0 /* 2^40 */, 1125899906842624.0 /* 2^50 */};
 
 template <int LOGN, int RC>
 struct Schedule {
   static constexpr double qmax = kClassQmax[RC];
-  static constexpr uint32_t fwd_small = forward_schedule(LOGN, qmax, 1.0);
-  static constexpr uint32_t fwd_big = forward_schedule(LOGN, qmax, qmax);
-  static constexpr uint32_t inv = inverse_schedule(LOGN, qmax, 0.75 * qmax + 4);
+  static constexpr FwdPlan small = forward_schedule(LOGN, qmax, 1.0);
+  static constexpr FwdPlan big = forward_schedule(LOGN, qmax, qmax);
+  static constexpr uint32_t fwd_small = small.mask;
+  static constexpr uint32_t fwd_big = big.mask;
+  static constexpr double inv_input =
+      pointwise_bound(qmax, small.bound > big.bound ? small.bound : big.bound);
+  static constexpr uint32_t inv = inverse_schedule(LOGN, qmax, inv_input);
+  static_assert(small.bound <= kFwdLimit && big.bound <= kFwdLimit, "forward bound");
 };
 
 // ---------------------------------------------------------------------------
@@ -132,6 +151,17 @@ CKKS_HD int opaque(int v) {
   return v;
 }
 
+// The same for a workgroup-uniform table pointer (kept in scalar registers): the
+// scalar base addresses of one pass's twiddle loads are formed inside the pass instead
+// of being hoisted out of the ciphertext and limb loops, where they would stay live.
+template <typename T>
+CKKS_HD const T *opaque_base(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+s"(p));
+#endif
+  return p;
+}
+
 // Keeps the device scheduler from interleaving consecutive stages: a pass compiles to
 // one straight-line block, and hoisting later stages' loads and arithmetic over earlier
 // ones raises register pressure past what two waves per SIMD can hold.
@@ -143,8 +173,9 @@ CKKS_HD void stage_fence() {
 
 // Forward (Cooley-Tukey) stages of one pass; reduce every value after stage s if bit s of RED.
 template <int LOGN, int LOGR, int PASS, uint32_t RED>
-CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ tw, double q, double qinv) {
+CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ tw_in, double q, double qinv) {
   const int tid = opaque(tid_in);
+  const double *__restrict__ tw = opaque_base(tw_in);
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;
@@ -174,8 +205,9 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 // Inverse (Gentleman-Sande) stages of one pass, in decreasing stage order; reduce the sum
 // outputs after stage s if bit s of RED.
 template <int LOGN, int LOGR, int PASS, uint32_t RED>
-CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ itw, double q, double qinv) {
+CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ itw_in, double q, double qinv) {
   const int tid = opaque(tid_in);
+  const double *__restrict__ itw = opaque_base(itw_in);
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;

@@ -19,9 +19,16 @@ struct Philox4 {
   uint64_t w[4];
 };
 
+// The key (k0, k1) must be uniform across the wavefront (it is a seed of the launch).
 CKKS_HD Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1) {
   constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
   constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#if defined(__HIP_DEVICE_COMPILE__)
+  // Every call of a launch has the same key; without this the compiler forms all twenty
+  // round keys once per kernel and keeps them in scalar registers throughout, which
+  // spills.  Here each call forms them as it goes (two scalar adds per round).
+  asm volatile("" : "+s"(k0), "+s"(k1));
+#endif
 #pragma unroll
   for (int r = 0; r < 10; r++) {
     uint64_t hi0, lo0, hi1, lo1;

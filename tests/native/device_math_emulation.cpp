@@ -178,6 +178,6 @@ int emu_gauss(uint64_t w, double sigma, int B) {
   std::vector<uint64_t> T = host::cdt_table(sigma, B, kCdtSlots);
   return gauss_of(w, T.data(), B);
 }
-uint32_t emu_fwd_mask(int log_n, double qmax, double in_bound) { return forward_schedule(log_n, qmax, in_bound); }
+uint32_t emu_fwd_mask(int log_n, double qmax, double in_bound) { return forward_schedule(log_n, qmax, in_bound).mask; }
 uint32_t emu_inv_mask(int log_n, double qmax, double in_bound) { return inverse_schedule(log_n, qmax, in_bound); }
 }

@@ -99,14 +99,14 @@ def test_emulated_ntt_product_matches_oracle(emu, oracle_mod, log_n, bits, logr)
 def test_reduction_schedules(emu):
     # 36-bit primes never need a reduction inside a forward transform; 50-bit primes do
     assert emu.emu_fwd_mask(13, 2.0**36, 1.0) == 0
-    assert emu.emu_inv_mask(13, 2.0**36, 0.75 * 2**36) == 0
+    assert emu.emu_inv_mask(13, 2.0**36, 2.0**36 + 4) == 0
     assert emu.emu_fwd_mask(13, 2.0**50, 2.0**50) != 0
-    assert emu.emu_inv_mask(13, 2.0**50, 0.75 * 2**50) != 0
+    assert emu.emu_inv_mask(13, 2.0**50, 2.0**50 + 4) != 0
     # a schedule derived for a larger modulus reduces at least where a smaller one needs to
     for log_n in (11, 12, 13, 14):
         for small, big in ((2.0**36, 2.0**40), (2.0**45, 2.0**50)):
             for f, inb in ((emu.emu_fwd_mask, lambda q: 1.0), (emu.emu_fwd_mask, lambda q: q),
-                           (emu.emu_inv_mask, lambda q: 0.75 * q + 4)):
+                           (emu.emu_inv_mask, lambda q: q + 4)):
                 m_small, m_big = f(log_n, small, inb(small)), f(log_n, big, inb(big))
                 # every prefix of stages of the big schedule has at least as many reductions
                 order = range(log_n) if f is emu.emu_fwd_mask else range(log_n - 1, -1, -1)
@@ -121,8 +121,9 @@ def test_fp64_modular_arithmetic_exact(emu, oracle_mod):
     rng = np.random.default_rng(7)
     for bits in (20, 36, 49, 50):
         q = oracle_mod.gen_primes(12, bits, 1)[0]
-        A = [0, 1, -1, q - 1, -(q - 1), 2**51 - 1, -(2**51 - 1), q // 2, -(q // 2)]
-        A += [int(x) for x in rng.integers(-(2**51) + 1, 2**51 - 1, 300)]
+        # forward-transform values reach 2^52 - 2^48 (the product precondition |a w / q| < 2^51)
+        A = [0, 1, -1, q - 1, -(q - 1), 2**51 - 1, -(2**51 - 1), q // 2, -(q // 2), 2**52 - 2**48, -(2**52 - 2**48)]
+        A += [int(x) for x in rng.integers(-(2**52) + 2**48, 2**52 - 2**48, 300)]
         W = [0, 1, -1, q // 2, -(q // 2), (q - 1) // 2]
         W += [int(x) for x in rng.integers(-(q // 2), q // 2 + 1, 30)]
         for a in A:
@@ -134,6 +135,9 @@ def test_fp64_modular_arithmetic_exact(emu, oracle_mod):
         for x in A + [2**52 - 1, -(2**52 - 1)]:
             r = emu.emu_reduce(float(x), float(q))
             assert (int(r) - x) % q == 0 and abs(r) <= q / 2 + 1
+        for x in [2**53 - 1, -(2**53 - 1), 2**53 - q, 2**52 + 12345] + [int(v) for v in rng.integers(2**52, 2**53, 50)]:
+            r = emu.emu_reduce(float(x), float(q))  # exact integers below 2^53
+            assert (int(r) - x) % q == 0 and abs(r) <= q / 2 + 2
             c = emu.emu_canon(float(x), float(q))
             assert c == x % q
             z = emu.emu_center(float(x), float(q))
