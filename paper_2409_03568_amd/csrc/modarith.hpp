@@ -13,8 +13,9 @@
 //   reduce(x):     |x| < 2^52      ->  x' = x (mod q), |x'| <= q/2 + 1
 //                  |x| < 2^53      ->  x' = x (mod q), |x'| <= q/2 + 2 (x an exact integer)
 //   mulmod(a, w):  |a*w/q| < 2^51  ->  r = a*w (mod q), |r| <= q/2 + |a*w| 2^-52 + 1
-// The NTT keeps every value below 2^51 in magnitude by reducing after the stages the
-// host selects (see host_math.cpp), which satisfies both preconditions.
+// The NTT keeps forward-transform values below 2^52 and inverse-transform values below
+// 2^51 by reducing after the stages its compile-time schedule selects (ntt.hpp), which
+// satisfies both preconditions.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -100,12 +101,18 @@ CKKS_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
   return p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
 }
 
+// 128-bit product as a chain of four 32x32+64 multiply-adds (one v_mad_u64_u32 each):
+// with t = a0 b0, u = a1 b0 + hi(t), v = a0 b1 + lo(u), w = a1 b1 + hi(u) (none of which
+// overflows 64 bits), a*b = lo(t) + 2^32 v + 2^64 w, so lo = (v << 32) | lo(t) and
+// hi = w + hi(v).
 CKKS_HD void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
-  const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
-  const uint64_t p00 = a0 * b0, p01 = a0 * b1, p10 = a1 * b0, p11 = a1 * b1;
-  const uint64_t mid = (p00 >> 32) + (uint32_t)p01 + (uint32_t)p10;
-  lo = (mid << 32) | (uint32_t)p00;
-  hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t t = (uint64_t)a0 * b0;
+  const uint64_t u = (uint64_t)a1 * b0 + (t >> 32);
+  const uint64_t v = (uint64_t)a0 * b1 + (uint32_t)u;
+  const uint64_t w = (uint64_t)a1 * b1 + (u >> 32);
+  lo = (v << 32) | (uint32_t)t;
+  hi = w + (v >> 32);
 }
 
 CKKS_HD uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) {

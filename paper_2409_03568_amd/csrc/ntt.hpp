@@ -151,16 +151,6 @@ CKKS_HD int opaque(int v) {
   return v;
 }
 
-// The same for a workgroup-uniform table pointer (kept in scalar registers): the
-// scalar base addresses of one pass's twiddle loads are formed inside the pass instead
-// of being hoisted out of the ciphertext and limb loops, where they would stay live.
-template <typename T>
-CKKS_HD const T *opaque_base(const T *p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  asm volatile("" : "+s"(p));
-#endif
-  return p;
-}
 
 // Keeps the device scheduler from interleaving consecutive stages: a pass compiles to
 // one straight-line block, and hoisting later stages' loads and arithmetic over earlier
@@ -173,9 +163,8 @@ CKKS_HD void stage_fence() {
 
 // Forward (Cooley-Tukey) stages of one pass; reduce every value after stage s if bit s of RED.
 template <int LOGN, int LOGR, int PASS, uint32_t RED>
-CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ tw_in, double q, double qinv) {
+CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ tw, double q, double qinv) {
   const int tid = opaque(tid_in);
-  const double *__restrict__ tw = opaque_base(tw_in);
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;
@@ -205,9 +194,8 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 // Inverse (Gentleman-Sande) stages of one pass, in decreasing stage order; reduce the sum
 // outputs after stage s if bit s of RED.
 template <int LOGN, int LOGR, int PASS, uint32_t RED>
-CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ itw_in, double q, double qinv) {
+CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ itw, double q, double qinv) {
   const int tid = opaque(tid_in);
-  const double *__restrict__ itw = opaque_base(itw_in);
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;
