@@ -10,6 +10,7 @@ beforehand (their build time is reported separately).  Prints one JSON line.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -21,6 +22,33 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: full-rate FP64 VALU lane-operations per second
 PEAK_VALU_OPS = 256 * 64 * 2.4e9
+
+# Sources of the plain-encryption kernel; the HBM traffic measured with hardware counters
+# (profiles/c2_step_hbm_counters.md) is reported only while they are unchanged.
+ENC_SOURCES = ["paper_2409_03568_amd/csrc/" + f for f in
+               ("k_ntt_impl.hpp", "k_ntt_13.hip", "ntt.hpp", "modarith.hpp", "philox.hpp", "internal.hpp")]
+COUNTERS_MD = os.path.join(ROOT, "profiles", "c2_step_hbm_counters.md")
+
+
+def measured_traffic():
+    """Bytes read + written per plain-encryption launch at this workload, from the counter
+    runs in profiles/, or None when the kernel's sources changed since they were taken."""
+    import hashlib
+
+    try:
+        text = open(COUNTERS_MD).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic k_encrypt_plain_c2 read_bytes=(\d+) write_bytes=(\d+) .* sources_sha256=([0-9a-f]+)", text)
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in ENC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != m.group(3):
+        return None
+    return int(m.group(1)) + int(m.group(2))
 
 
 def parse():
@@ -377,9 +405,22 @@ def main():
     if t_plain > 0:
         achieved = ops / t_plain / 1e12
         peak = PEAK_VALU_OPS / 1e12
-        roofline = {"bound": "alu", "kernel": "k_encrypt<13,5> (fused plain encryption)", "achieved": round(achieved, 3),
-                    "peak": round(peak, 3), "unit": "TVALUop/s (FP64)", "frac": round(achieved / peak, 4),
-                    "traffic": None}
+        width = ctx.ntt_width()
+        roofline = {"bound": "alu",
+                    "kernel": "k_encrypt<13, %d, 1, 0, false> (fused plain encryption, %d values per thread)"
+                              % (4 if width == 16 else 5, width),
+                    "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TVALUop/s (FP64)",
+                    "frac": round(achieved / peak, 4),
+                    "traffic": measured_traffic() if width == 16 else None}
+    # the HBM-bound kernels against the 8 TB/s peak (algorithmic bytes: radix and value
+    # encryption write S per pixel, the filter reads S and writes S (L-1)/L per pixel)
+    hbm = {}
+    if phase_ms["radix"] > 0:
+        hbm["radix_gather"] = {"GBps": round(n * S / (phase_ms["radix"] / 1e3) / 1e9, 1)}
+    if phase_ms["filter"] > 0:
+        hbm["mean_filter"] = {"GBps": round(n * S * (1 + (c.num_primes - 1) / c.num_primes) / (phase_ms["filter"] / 1e3) / 1e9, 1)}
+    for v in hbm.values():
+        v["frac_of_8TBps"] = round(v["GBps"] / PEAK_HBM_GBS, 4)
 
     def gbs(nbytes, ms):
         return round(nbytes / (ms / 1e3) / 1e9, 1) if ms > 0 else None
@@ -416,6 +457,7 @@ def main():
         "cache_build_ms": {k: round(v, 3) for k, v in cache_ms.items()},
         "filter_decrypt_max_err": ok,
         "roofline": roofline,
+        "hbm_kernels": hbm,
     }
     del ct, flt, dec, radix, value
     ctx.close()
