@@ -30,25 +30,27 @@ ENC_SOURCES = ["paper_2409_03568_amd/csrc/" + f for f in
 COUNTERS_MD = os.path.join(ROOT, "profiles", "c2_step_hbm_counters.md")
 
 
-def measured_traffic():
+def measured_traffic(width):
     """Bytes read + written per plain-encryption launch at this workload, from the counter
-    runs in profiles/, or None when the kernel's sources changed since they were taken."""
+    runs in profiles/, or None when they were taken at another NTT width or the kernel's
+    sources changed since."""
     import hashlib
 
     try:
         text = open(COUNTERS_MD).read()
     except OSError:
         return None
-    m = re.search(r"traffic k_encrypt_plain_c2 read_bytes=(\d+) write_bytes=(\d+) .* sources_sha256=([0-9a-f]+)", text)
-    if not m:
+    m = re.search(r"traffic k_encrypt_plain_c2 width=(\d+) read_bytes=(\d+) write_bytes=(\d+) .* "
+                  r"sources_sha256=([0-9a-f]+)", text)
+    if not m or int(m.group(1)) != width:
         return None
     h = hashlib.sha256()
     for f in ENC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != m.group(3):
+    if h.hexdigest() != m.group(4):
         return None
-    return int(m.group(1)) + int(m.group(2))
+    return int(m.group(2)) + int(m.group(3))
 
 
 def parse():
@@ -408,10 +410,10 @@ def main():
         width = ctx.ntt_width()
         roofline = {"bound": "alu",
                     "kernel": "k_encrypt<13, %d, 1, 0, false> (fused plain encryption, %d values per thread)"
-                              % (4 if width == 16 else 5, width),
+                              % (width.bit_length() - 1, width),
                     "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TVALUop/s (FP64)",
                     "frac": round(achieved / peak, 4),
-                    "traffic": measured_traffic() if width == 16 else None}
+                    "traffic": measured_traffic(width)}
     # the HBM-bound kernels against the 8 TB/s peak (algorithmic bytes: radix and value
     # encryption write S per pixel, the filter reads S and writes S (L-1)/L per pixel)
     hbm = {}

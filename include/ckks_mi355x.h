@@ -134,9 +134,9 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out);
 void ckks_context_destroy(ckks_ctx *ctx);
 
 /* Tuning of the NTT kernels (encryption, decryption, keys): each thread of a workgroup
- * holds values_per_thread ring coefficients (16 or 32), so a workgroup has
- * N / values_per_thread threads.  Results are identical for every setting; only speed
- * differs.  CKKS_EINVAL for other values. */
+ * holds values_per_thread ring coefficients (8, 16 or 32), so a workgroup has
+ * N / values_per_thread threads (at most 1024: 8 needs N <= 8192).  Results are
+ * identical for every setting; only speed differs.  CKKS_EINVAL for other values. */
 int ckks_context_set_ntt_width(ckks_ctx *ctx, uint32_t values_per_thread);
 int ckks_context_get_ntt_width(const ckks_ctx *ctx, uint32_t *values_per_thread);
 
@@ -253,7 +253,7 @@ int ckks_stream_sync(ckks_ctx *ctx, void *stream);
 /* ---- autotuning ----
  * Times the NTT kernels (encryption, Sec. 2.2.2: one forward and two inverse
  * transforms per limb; decryption: one forward and one inverse on limb 0) at each
- * supported register blocking (16 or 32 values per thread) on trial_cts synthetic
+ * supported register blocking (8, 16 or 32 values per thread) on trial_cts synthetic
  * ciphertexts, keeps the faster width for each kernel on this context, and reports the
  * timings.  The choice changes speed only, never results.  Enqueues on the null stream
  * and synchronizes; allocates and frees its own scratch buffers.
@@ -261,7 +261,7 @@ int ckks_stream_sync(ckks_ctx *ctx, void *stream);
 typedef struct {
   uint32_t encrypt_width, decrypt_width;  /* chosen values per thread */
   uint32_t trial_cts, reserved;
-  double encrypt_ms[2], decrypt_ms[2];    /* best of 3 runs: [0] 16, [1] 32 values per thread */
+  double encrypt_ms[3], decrypt_ms[3];    /* best of 3 runs: [0] 8, [1] 16, [2] 32 values per thread */
 } ckks_tune_report;
 
 int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out);

@@ -68,7 +68,7 @@ class ckks_server_stats_t(C.Structure):
 
 class ckks_tune_report_t(C.Structure):
     _fields_ = [("encrypt_width", C.c_uint32), ("decrypt_width", C.c_uint32), ("trial_cts", C.c_uint32),
-                ("reserved", C.c_uint32), ("encrypt_ms", C.c_double * 2), ("decrypt_ms", C.c_double * 2)]
+                ("reserved", C.c_uint32), ("encrypt_ms", C.c_double * 3), ("decrypt_ms", C.c_double * 3)]
 
 
 class ckks_pipeline_config_t(C.Structure):
@@ -418,8 +418,8 @@ class Context:
         r = ckks_tune_report_t()
         _check(lib().ckks_autotune(self.handle, int(trial_cts), C.byref(r)))
         return {"encrypt_width": r.encrypt_width, "decrypt_width": r.decrypt_width, "trial_cts": r.trial_cts,
-                "encrypt_ms": {16: r.encrypt_ms[0], 32: r.encrypt_ms[1]},
-                "decrypt_ms": {16: r.decrypt_ms[0], 32: r.decrypt_ms[1]}}
+                "encrypt_ms": {8: r.encrypt_ms[0], 16: r.encrypt_ms[1], 32: r.encrypt_ms[2]},
+                "decrypt_ms": {8: r.decrypt_ms[0], 16: r.decrypt_ms[1], 32: r.decrypt_ms[2]}}
 
 
 class Cache:

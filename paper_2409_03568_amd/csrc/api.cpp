@@ -257,8 +257,11 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   }
   // the transforms' lazy-reduction schedule is compiled per class of prime sizes
   c->rc = qmax < 1099511627776.0 ? 0 : 1;
-  // values per NTT thread: 16 (twice the threads, half the registers) measured faster
-  c->logr_enc = c->logr_dec = 4;
+  // values per NTT thread (measured on MI355X at N = 8192): encryption is fastest with 8
+  // (16 waves per ciphertext at 127 VGPRs, 4 waves per SIMD), decryption with 16 (two
+  // 8-wave workgroups per CU); 8 needs N / 8 <= 1024 threads
+  c->logr_enc = N / 8 <= 1024 ? 3 : 4;
+  c->logr_dec = 4;
   hipError_t e = hipSuccess;
   DevTables &d = c->dev;
   if (e == hipSuccess) e = dev_alloc(&d.tw_fwd, (size_t)L * N);
@@ -317,8 +320,10 @@ void ckks_context_destroy(ckks_ctx *ctx) {
 int ckks_context_set_ntt_width(ckks_ctx *ctx, uint32_t values_per_thread) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
-  if (values_per_thread != 16 && values_per_thread != 32) return fail(CKKS_EINVAL, "values_per_thread must be 16 or 32");
-  ctx->logr_enc = ctx->logr_dec = values_per_thread == 16 ? 4 : 5;
+  if (values_per_thread != 8 && values_per_thread != 16 && values_per_thread != 32)
+    return fail(CKKS_EINVAL, "values_per_thread must be 8, 16 or 32");
+  if (ctx->N / values_per_thread > 1024) return fail(CKKS_EINVAL, "N / values_per_thread exceeds 1024 threads");
+  ctx->logr_enc = ctx->logr_dec = values_per_thread == 8 ? 3 : (values_per_thread == 16 ? 4 : 5);
   return CKKS_OK;
 }
 

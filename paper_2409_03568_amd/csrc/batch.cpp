@@ -247,9 +247,10 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   const int keep_enc = ctx->logr_enc, keep_dec = ctx->logr_dec;
-  double enc_ms[2] = {INFINITY, INFINITY}, dec_ms[2] = {INFINITY, INFINITY};
-  for (int w = 0; w < 2 && e == hipSuccess; w++) {
-    ctx->logr_enc = ctx->logr_dec = 4 + w;
+  double enc_ms[3] = {INFINITY, INFINITY, INFINITY}, dec_ms[3] = {INFINITY, INFINITY, INFINITY};
+  for (int w = 0; w < 3 && e == hipSuccess; w++) {
+    if ((ctx->N >> (3 + w)) > 1024) continue;  // more threads than a workgroup holds
+    ctx->logr_enc = ctx->logr_dec = 3 + w;
     EncJob job;
     job.px = px;
     job.n = trial_cts;
@@ -282,13 +283,18 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
     ctx->logr_dec = keep_dec;
     return api_fail(CKKS_EDEVICE, "autotune: %s", hipGetErrorString(e));
   }
-  ctx->logr_enc = enc_ms[1] < enc_ms[0] ? 5 : 4;
-  ctx->logr_dec = dec_ms[1] < dec_ms[0] ? 5 : 4;
+  int be = 0, bd = 0;
+  for (int w = 1; w < 3; w++) {
+    if (enc_ms[w] < enc_ms[be]) be = w;
+    if (dec_ms[w] < dec_ms[bd]) bd = w;
+  }
+  ctx->logr_enc = 3 + be;
+  ctx->logr_dec = 3 + bd;
   out->encrypt_width = 1u << ctx->logr_enc;
   out->decrypt_width = 1u << ctx->logr_dec;
   out->trial_cts = trial_cts;
   out->reserved = 0;
-  for (int w = 0; w < 2; w++) {
+  for (int w = 0; w < 3; w++) {
     out->encrypt_ms[w] = enc_ms[w];
     out->decrypt_ms[w] = dec_ms[w];
   }

@@ -254,11 +254,18 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 // decryption of limb 0 and decoding of slot 0:
 //   d = c0 + INTT(NTT(c1) * s_hat); out = sum_j center(d_j) cos(pi j/N) / scale
 // ---------------------------------------------------------------------------
-// Register budget: enough for two workgroups per CU (the LDS of two fits for N <= 8192),
-// so one workgroup's waves compute while the other's wait at a barrier.
+// Register budget: enough waves per SIMD for as many workgroups as the LDS admits on a
+// CU (at most two), so one workgroup's waves compute while another's wait at a barrier.
+template <int LOGN, int LOGR>
+constexpr int decrypt_waves_per_eu() {
+  constexpr int wgs = (int)((160 * 1024) / Shape<LOGN, LOGR>::lds_bytes) >= 2 ? 2 : 1;
+  constexpr int w = wgs * (1 << (LOGN - LOGR)) / 256;
+  return w < 1 ? 1 : w;
+}
+
 template <int LOGN, int LOGR, int RC>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
-    __attribute__((amdgpu_waves_per_eu((1 << (LOGN - LOGR)) >= 256 ? (1 << (LOGN - LOGR)) / 128 : 1)))
+    __attribute__((amdgpu_waves_per_eu(decrypt_waves_per_eu<LOGN, LOGR>())))
     k_decrypt(const uint64_t *__restrict__ cts, uint64_t n, int level, double inv_scale, double *__restrict__ out,
               const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
@@ -370,6 +377,9 @@ template <int LOGN>
 struct RingLaunch {
   template <typename F>
   static hipError_t pick(const ckks_ctx *c, int logr, F f) {
+    if constexpr (LOGN - 3 <= 10) {  // 8 values per thread: N/8 threads, at most 1024
+      if (logr == 3) return c->rc ? f(Launch<LOGN, 3, 1>{}) : f(Launch<LOGN, 3, 0>{});
+    }
     if (logr == 4) return c->rc ? f(Launch<LOGN, 4, 1>{}) : f(Launch<LOGN, 4, 0>{});
     if (logr == 5) return c->rc ? f(Launch<LOGN, 5, 1>{}) : f(Launch<LOGN, 5, 0>{});
     return hipErrorInvalidValue;

@@ -221,18 +221,25 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
   }
 }
 
+// The element index is the bitwise OR of a thread part, elem_index(tid, 0), and a
+// register part, elem_index(0, r), on disjoint bits (the thread index and the register
+// index fill different bit fields of it), and the padded position keeps that split:
+// lds_pos(a | b) = lds_pos(a) + lds_pos(b) for disjoint a, b.  So each thread computes one
+// base address per exchange and the registers use compile-time offsets from it.
 template <int LOGN, int LOGR, int PASS>
 CKKS_HD void lds_store(double *lds, const double (&x)[1 << LOGR], int tid_in) {
   const int tid = opaque(tid_in);
+  double *base = lds + lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>((unsigned)tid, 0));
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) lds[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(tid, r))] = x[r];
+  for (int r = 0; r < (1 << LOGR); r++) base[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(0, r))] = x[r];
 }
 
 template <int LOGN, int LOGR, int PASS>
 CKKS_HD void lds_load(const double *lds, double (&x)[1 << LOGR], int tid_in) {
   const int tid = opaque(tid_in);
+  const double *base = lds + lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>((unsigned)tid, 0));
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) x[r] = lds[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(tid, r))];
+  for (int r = 0; r < (1 << LOGR); r++) x[r] = base[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(0, r))];
 }
 
 // Passes 1..NPASS-1 of the forward transform (pass 0 is run by the caller on the

@@ -45,7 +45,12 @@ void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double
       for (int t = 0; t < S::T; t++) {
         for (int r = 0; r < S::R; r++) {
           x[r] = X[t][r];
-          hit[lds_pos<LOGR>(elem_index<LOGN, LOGR, P - 1>(t, r))]++;
+          const unsigned e = elem_index<LOGN, LOGR, P - 1>(t, r);
+          hit[lds_pos<LOGR>(e)]++;
+          // the split the kernels use: thread base plus a per-register offset
+          const unsigned et = elem_index<LOGN, LOGR, P - 1>(t, 0), er = elem_index<LOGN, LOGR, P - 1>(0, r);
+          if ((et & er) != 0 || (et | er) != e || lds_pos<LOGR>(e) != lds_pos<LOGR>(et) + lds_pos<LOGR>(er))
+            g_lds_bijective = false;
         }
         lds_store<LOGN, LOGR, P - 1>(lds.data(), x, t);
       }
@@ -135,6 +140,7 @@ int negacyclic(const int64_t *a, const uint64_t *b, uint64_t *c, uint64_t q, uin
 template <int LOGN>
 int negacyclic_shape(const int64_t *a, const uint64_t *b, uint64_t *c, uint64_t q, uint64_t psi, int a_small, int logr,
                      int rc) {
+  if (logr == 3) return rc ? negacyclic<LOGN, 3, 1>(a, b, c, q, psi, a_small) : negacyclic<LOGN, 3, 0>(a, b, c, q, psi, a_small);
   if (logr == 4) return rc ? negacyclic<LOGN, 4, 1>(a, b, c, q, psi, a_small) : negacyclic<LOGN, 4, 0>(a, b, c, q, psi, a_small);
   if (logr == 5) return rc ? negacyclic<LOGN, 5, 1>(a, b, c, q, psi, a_small) : negacyclic<LOGN, 5, 0>(a, b, c, q, psi, a_small);
   return -1;

@@ -68,8 +68,9 @@ def _u64(a):
     return np.ascontiguousarray(a, dtype=np.uint64)
 
 
-@pytest.mark.parametrize("log_n,bits,logr", [(11, 30, 5), (12, 36, 5), (12, 36, 4), (13, 50, 5), (13, 50, 4),
-                                            (13, 40, 4), (14, 50, 5), (14, 50, 4), (11, 49, 4)])
+@pytest.mark.parametrize("log_n,bits,logr", [(11, 30, 5), (12, 36, 5), (12, 36, 4), (12, 36, 3), (13, 50, 5),
+                                            (13, 50, 4), (13, 50, 3), (13, 40, 4), (14, 50, 5), (14, 50, 4),
+                                            (11, 49, 4), (11, 49, 3)])
 def test_emulated_ntt_product_matches_oracle(emu, oracle_mod, log_n, bits, logr):
     N = 1 << log_n
     rng = np.random.default_rng(log_n * 100 + bits)

@@ -141,7 +141,7 @@ def test_autotune_keeps_results(env, oracle_mod):
     px = torch.from_numpy(np.arange(64, dtype=np.uint8)).cuda()
     before = ctx.encrypt_pixels(px, (4, 4)).to_numpy().copy()
     rep = ctx.autotune(512)
-    assert rep["encrypt_width"] in (16, 32) and rep["decrypt_width"] in (16, 32)
+    assert rep["encrypt_width"] in (8, 16, 32) and rep["decrypt_width"] in (8, 16, 32)
     assert all(v > 0 for v in rep["encrypt_ms"].values()) and all(v > 0 for v in rep["decrypt_ms"].values())
     after = ctx.encrypt_pixels(px, (4, 4))
     torch.cuda.synchronize()

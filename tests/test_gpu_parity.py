@@ -153,7 +153,7 @@ def test_ntt_width_invariance(P, oracle_mod, W, cfg):
     c = W.CONFIGS[cfg]
     px = W.config_image(cfg).reshape(-1)[:96]
     outs, decs, keys = [], [], []
-    for width in (16, 32):
+    for width in (8, 16, 32):
         ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
         ctx.set_ntt_width(width)
         assert ctx.ntt_width() == width
@@ -162,16 +162,17 @@ def test_ntt_width_invariance(P, oracle_mod, W, cfg):
         cts = ctx.encrypt_pixels(_dev(px), W.job_seed(cfg), first_index=7)
         outs.append(_np(cts))
         decs.append(ctx.decrypt_pixels(cts).cpu().numpy())
-    assert np.array_equal(keys[0][0], keys[1][0]) and np.array_equal(keys[0][1], keys[1][1])
-    assert np.array_equal(outs[0], outs[1])
-    # the decoded value is a floating-point sum whose order follows the workgroup shape
-    assert np.max(np.abs(decs[0] - decs[1])) < 1e-9
+    for i in (1, 2):
+        assert np.array_equal(keys[0][0], keys[i][0]) and np.array_equal(keys[0][1], keys[i][1])
+        assert np.array_equal(outs[0], outs[i])
+        # the decoded value is a floating-point sum whose order follows the workgroup shape
+        assert np.max(np.abs(decs[0] - decs[i])) < 1e-9
     o = oracle_mod.Oracle(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
     o.keygen(W.keygen_seed(cfg))
     for t in (0, 50, 95):
         assert np.array_equal(outs[0][t], o.encrypt(int(px[t]), W.job_seed(cfg), 7 + t))
     with pytest.raises(P.CkksError):
-        ctx.set_ntt_width(8)
+        ctx.set_ntt_width(64)
 
 
 def test_noiseless_roundtrip(P, oracle_mod, W):
