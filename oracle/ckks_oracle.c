@@ -136,6 +136,19 @@ int orc_params_init(orc_params *P, int log_n, int L, int bits, int log_scale, do
     P->psi[i] = orc_primitive_2n_root(P->q[i], log_n);
     if (!P->psi[i]) return -3;
   }
+  /* special prime of key switching: the largest prime of the same form (bits, 1 mod 2N)
+     that is not a ciphertext prime */
+  {
+    uint64_t cand[ORC_MAX_LIMBS + 1];
+    const int n = orc_gen_primes(log_n, bits, L + 1, cand);
+    P->qP = 0;
+    for (int k = 0; k < n && !P->qP; k++) {
+      int used = 0;
+      for (int i = 0; i < L; i++) used |= (cand[k] == P->q[i]);
+      if (!used) P->qP = cand[k];
+    }
+    if (P->qP) P->psiP = orc_primitive_2n_root(P->qP, log_n);
+  }
   if (orc_cdt_table(sigma, P->B, P->cdt) != 0) return -4;
   return 0;
 }
@@ -679,4 +692,121 @@ int orc_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* ciphertext multiplication (Sec. 2.2.3): tensor product, relinearization   */
+/* by hybrid key switching with the special prime qP, one digit per limb.   */
+/* ------------------------------------------------------------------------ */
+static uint64_t prime_at(const orc_params *P, int j) { return j < P->L ? P->q[j] : P->qP; }
+static uint64_t root_at(const orc_params *P, int j) { return j < P->L ? P->psi[j] : P->psiP; }
+
+void orc_relin_keygen(const orc_params *P, const int64_t *s, const uint64_t seed[2], uint64_t *evk) {
+  const int N = 1 << P->log_n, L = P->L;
+  int64_t *e = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+  uint64_t *si = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+  uint64_t *s2 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+  uint64_t *as = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+  for (int i = 0; i < L; i++) {
+    orc_sample_gauss(P, seed, 0, (uint64_t)(ORC_TAG_RK_E0 + i), e);
+    for (int j = 0; j <= L; j++) {
+      const uint64_t p = prime_at(P, j), psi = root_at(P, j);
+      uint64_t *b = evk + (((size_t)i * (L + 1) + j) * 2) * N, *a = b + N;
+      orc_sample_uniform(seed, 0, (uint64_t)(ORC_TAG_RK_A0 + 32 * i + j), N, p, a);
+      for (int k = 0; k < N; k++) si[k] = residue(s[k], p);
+      orc_negacyclic_mul(a, si, as, N, p, psi);
+      for (int k = 0; k < N; k++) b[k] = addmod(submod(0, as[k], p), residue(e[k], p), p);
+      if (j == i) { /* + (qP mod q_i) * s^2 */
+        orc_negacyclic_mul(si, si, s2, N, p, psi);
+        const uint64_t pm = P->qP % p;
+        for (int k = 0; k < N; k++) b[k] = addmod(b[k], mulmod(pm, s2[k], p), p);
+      }
+    }
+  }
+  free(e);
+  free(si);
+  free(s2);
+  free(as);
+}
+
+void orc_tensor(const orc_params *P, const uint64_t *a, const uint64_t *b, int level, uint64_t *d) {
+  const int N = 1 << P->log_n;
+  uint64_t *t = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+  for (int j = 0; j < level; j++) {
+    const uint64_t q = P->q[j], psi = P->psi[j];
+    const uint64_t *a0 = a + (size_t)j * N, *a1 = a + ((size_t)level + j) * N;
+    const uint64_t *b0 = b + (size_t)j * N, *b1 = b + ((size_t)level + j) * N;
+    uint64_t *d0 = d + (size_t)j * N, *d1 = d + ((size_t)level + j) * N, *d2 = d + ((size_t)2 * level + j) * N;
+    orc_negacyclic_mul(a0, b0, d0, N, q, psi);
+    orc_negacyclic_mul(a0, b1, d1, N, q, psi);
+    orc_negacyclic_mul(a1, b0, t, N, q, psi);
+    for (int k = 0; k < N; k++) d1[k] = addmod(d1[k], t[k], q);
+    orc_negacyclic_mul(a1, b1, d2, N, q, psi);
+  }
+  free(t);
+}
+
+void orc_key_switch(const orc_params *P, const uint64_t *evk, const uint64_t *d2, int level, uint64_t *acc) {
+  const int N = 1 << P->log_n, L = P->L;
+  uint64_t *x = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+  uint64_t *t = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+  for (int jj = 0; jj <= level; jj++) {
+    const int j = jj < level ? jj : L; /* key index of the prime */
+    const uint64_t p = prime_at(P, j), psi = root_at(P, j);
+    uint64_t *acc0 = acc + (size_t)jj * N, *acc1 = acc + ((size_t)(level + 1) + jj) * N;
+    memset(acc0, 0, sizeof(uint64_t) * (size_t)N);
+    memset(acc1, 0, sizeof(uint64_t) * (size_t)N);
+    for (int i = 0; i < level; i++) {
+      const uint64_t *di = d2 + (size_t)i * N;
+      for (int k = 0; k < N; k++) x[k] = di[k] % p; /* the digit as an integer in [0, q_i) */
+      const uint64_t *kb = evk + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
+      orc_negacyclic_mul(x, kb, t, N, p, psi);
+      for (int k = 0; k < N; k++) acc0[k] = addmod(acc0[k], t[k], p);
+      orc_negacyclic_mul(x, ka, t, N, p, psi);
+      for (int k = 0; k < N; k++) acc1[k] = addmod(acc1[k], t[k], p);
+    }
+  }
+  free(x);
+  free(t);
+}
+
+void orc_mod_down(const orc_params *P, const uint64_t *acc, int level, uint64_t *out) {
+  const int N = 1 << P->log_n;
+  const uint64_t qP = P->qP;
+  for (int k = 0; k < 2; k++) {
+    const uint64_t *aP = acc + ((size_t)k * (level + 1) + level) * N;
+    for (int j = 0; j < level; j++) {
+      const uint64_t q = P->q[j], pinv = invmod(qP % q, q);
+      const uint64_t *aj = acc + ((size_t)k * (level + 1) + j) * N;
+      uint64_t *o = out + ((size_t)k * level + j) * N;
+      for (int c = 0; c < N; c++) {
+        /* centered residue of x mod qP, reduced mod q */
+        const uint64_t xp = aP[c];
+        const uint64_t xp_q = xp > qP / 2 ? submod(0, (qP - xp) % q, q) : xp % q;
+        o[c] = mulmod(submod(aj[c], xp_q, q), pinv, q);
+      }
+    }
+  }
+}
+
+void orc_mul(const orc_params *P, const uint64_t *evk, const uint64_t *a, const uint64_t *b, int level,
+             uint64_t *out) {
+  const int N = 1 << P->log_n;
+  uint64_t *d = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)3 * level * N);
+  uint64_t *acc = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)2 * (level + 1) * N);
+  uint64_t *ks = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)2 * level * N);
+  orc_tensor(P, a, b, level, d);
+  orc_key_switch(P, evk, d + (size_t)2 * level * N, level, acc);
+  orc_mod_down(P, acc, level, ks);
+  for (int k = 0; k < 2; k++)
+    for (int j = 0; j < level; j++) {
+      const uint64_t q = P->q[j];
+      for (int c = 0; c < N; c++) {
+        const size_t idx = ((size_t)k * level + j) * N + c;
+        out[idx] = addmod(d[idx], ks[idx], q);
+      }
+    }
+  free(d);
+  free(acc);
+  free(ks);
 }

@@ -32,7 +32,9 @@ extern "C" {
 /* Stream tags (counter word 1). */
 enum {
   ORC_TAG_V = 1, ORC_TAG_E0 = 2, ORC_TAG_E1 = 3, ORC_TAG_AUX = 4,
-  ORC_TAG_SK = 16, ORC_TAG_EK = 17, ORC_TAG_A0 = 32
+  ORC_TAG_SK = 16, ORC_TAG_EK = 17, ORC_TAG_A0 = 32,
+  ORC_TAG_RK_E0 = 48, /* + digit i: error of key-switching key i */
+  ORC_TAG_RK_A0 = 64  /* + 32 digit + prime index: uniform part of key-switching key i */
 };
 /* Cache entry indices t under the cache seed. */
 enum { ORC_RADIX_BASE_T = 0, ORC_VALUE_BASE_T = 256, ORC_POOL_BASE_T = 512 };
@@ -46,6 +48,8 @@ typedef struct {
   uint64_t q[ORC_MAX_LIMBS];   /* primes, descending */
   uint64_t psi[ORC_MAX_LIMBS]; /* a primitive 2N-th root of unity mod q_i */
   uint64_t cdt[2 * ORC_MAX_B]; /* cumulative table, 2B entries */
+  uint64_t qP;                 /* special prime of key switching (not one of the q_i) */
+  uint64_t psiP;               /* a primitive 2N-th root of unity mod qP */
 } orc_params;
 
 /* ---- parameters ---- */
@@ -85,6 +89,28 @@ int orc_mul_const(const orc_params *P, const uint64_t *a, int level, double scal
 int orc_add_const(const orc_params *P, uint64_t *a, int level, double scale, double b);
 int orc_rescale(const orc_params *P, const uint64_t *in, int level, double scale, uint64_t *out,
                 double *out_scale);
+
+/* ---- ciphertext multiplication (Sec. 2.2.3: tensor product, relinearization) ----
+ * Relinearization is RNS hybrid key switching with the special prime qP and one digit per
+ * ciphertext prime.  Key-switching key i (i < L) has, for every prime p_j of
+ * {q_0..q_{L-1}, qP} (j = L is qP), the pair
+ *   ( -a_ij * s + e_i + [j == i] (qP mod q_i) s^2 ,  a_ij )  mod p_j,
+ * i.e. (-a s + e_i + qP g_i s^2, a) mod qP*Q with g_i = 1 mod q_i, 0 mod q_j (j != i).
+ * a_ij: uniform stream (seed, 0, ORC_TAG_RK_A0 + 32 i + j); e_i: Gaussian stream
+ * (seed, 0, ORC_TAG_RK_E0 + i), the same integers in every prime.
+ * Layout evk[i][j][2][N], canonical residues, coefficient domain.                       */
+void orc_relin_keygen(const orc_params *P, const int64_t *s, const uint64_t seed[2], uint64_t *evk);
+/* d[3][level][N] = (a0 b0, a0 b1 + a1 b0, a1 b1) per limb (negacyclic products). */
+void orc_tensor(const orc_params *P, const uint64_t *a, const uint64_t *b, int level, uint64_t *d);
+/* acc[2][level+1][N]: sum over digits i < level of (d2 limb i, lifted to p_j) * key i,
+ * for the primes q_0..q_{level-1} then qP (index level). */
+void orc_key_switch(const orc_params *P, const uint64_t *evk, const uint64_t *d2, int level, uint64_t *acc);
+/* out[2][level][N] = (x - [x]_qP) / qP mod q_j for the value x with residues acc[k][.][.]
+ * ([x]_qP centered), i.e. x / qP rounded to nearest. */
+void orc_mod_down(const orc_params *P, const uint64_t *acc, int level, uint64_t *out);
+/* out = (d0, d1) + ModDown(KeySwitch(d2)): the relinearized product, scale sa * sb. */
+void orc_mul(const orc_params *P, const uint64_t *evk, const uint64_t *a, const uint64_t *b, int level,
+             uint64_t *out);
 
 /* ---- caching (Sec. 3.2) and randomness (Sec. 3.3) ---- */
 void orc_radix_entries(const orc_params *P, const uint64_t *pk, int r, int D, const uint64_t cache_seed[2],

@@ -52,6 +52,7 @@ class _Params(C.Structure):
         ("sigma", C.c_double),
         ("q", C.c_uint64 * MAX_LIMBS), ("psi", C.c_uint64 * MAX_LIMBS),
         ("cdt", C.c_uint64 * (2 * MAX_B)),
+        ("qP", C.c_uint64), ("psiP", C.c_uint64),
     ]
 
 
@@ -106,6 +107,11 @@ def lib():
             "orc_encrypt_batch": (None, [P, u64p, u8p, C.c_uint64, u64p, C.c_uint64, u64p]),
             "orc_decrypt_batch": (None, [P, i64p, u64p, C.c_uint64, C.c_int, C.c_double, dp, ip]),
             "orc_num_threads": (C.c_int, []),
+            "orc_relin_keygen": (None, [P, i64p, u64p, u64p]),
+            "orc_tensor": (None, [P, u64p, u64p, C.c_int, u64p]),
+            "orc_key_switch": (None, [P, u64p, u64p, C.c_int, u64p]),
+            "orc_mod_down": (None, [P, u64p, C.c_int, u64p]),
+            "orc_mul": (None, [P, u64p, u64p, u64p, C.c_int, u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -240,8 +246,11 @@ class Oracle:
         self.B = int(self.P.B)
         self.cdt = np.array([int(self.P.cdt[k]) for k in range(2 * self.B)], dtype=np.uint64)
         self.scale = float(2.0**self.log_scale)
+        self.qP = int(self.P.qP)
+        self.psiP = int(self.P.psiP)
         self.s = None
         self.pk = None
+        self.evk = None
 
     # -- sizes ---------------------------------------------------------------
     def ct_words(self, level: int | None = None) -> int:
@@ -392,6 +401,49 @@ class Oracle:
         if rc:
             raise ValueError("rescale needs level >= 2")
         return out, sc.value
+
+    # -- ciphertext multiplication ------------------------------------------------
+    def relin_keygen(self, seed) -> np.ndarray:
+        """Key-switching keys of s^2: evk[i][j][2][N] (digit i < L, prime j <= L, j = L is qP)."""
+        k, kp = _seed(seed)
+        s, sp = _i64(self.s)
+        evk = np.zeros(self.L * (self.L + 1) * 2 * self.N, dtype=np.uint64)
+        lib().orc_relin_keygen(self._p, sp, kp, evk.ctypes.data_as(C.POINTER(C.c_uint64)))
+        self.evk = evk
+        return evk.reshape(self.L, self.L + 1, 2, self.N)
+
+    def tensor(self, a, b, level=None) -> np.ndarray:
+        level = self.L if level is None else level
+        a, ap = _u64(a)
+        b, bp = _u64(b)
+        d = np.zeros(3 * level * self.N, dtype=np.uint64)
+        lib().orc_tensor(self._p, ap, bp, level, d.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return d
+
+    def key_switch(self, d2, level=None, evk=None) -> np.ndarray:
+        level = self.L if level is None else level
+        e, ep = _u64(self.evk if evk is None else evk)
+        d2, dp = _u64(d2)
+        acc = np.zeros(2 * (level + 1) * self.N, dtype=np.uint64)
+        lib().orc_key_switch(self._p, ep, dp, level, acc.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return acc
+
+    def mod_down(self, acc, level=None) -> np.ndarray:
+        level = self.L if level is None else level
+        acc, ap = _u64(acc)
+        out = np.zeros(2 * level * self.N, dtype=np.uint64)
+        lib().orc_mod_down(self._p, ap, level, out.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return out
+
+    def mul(self, a, b, level=None, evk=None) -> np.ndarray:
+        """Relinearized product of two ciphertexts at one level (scale = product of scales)."""
+        level = self.L if level is None else level
+        e, ep = _u64(self.evk if evk is None else evk)
+        a, ap = _u64(a)
+        b, bp = _u64(b)
+        out = np.zeros(2 * level * self.N, dtype=np.uint64)
+        lib().orc_mul(self._p, ep, ap, bp, level, out.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return out
 
     # -- caches -------------------------------------------------------------------
     def radix_entries(self, r: int, D: int, cache_seed) -> np.ndarray:

@@ -549,3 +549,150 @@ def test_paper_psnr_values(oracle_mod):
         assert abs(oracle_mod.psnr(r["mse"]) - r["psnr_db"]) < 0.05
     assert abs(np.mean([r["mse"] for r in g["table2"]]) - g["average"]["mse"]) < 1e-3
     assert abs(oracle_mod.mse([0, 10], [3, 14]) - 12.5) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# ciphertext multiplication: tensor product, key switching, ModDown (Sec. 2.2.3)
+# ---------------------------------------------------------------------------
+def _negacyclic_int(a, b):
+    """Negacyclic product of two integer sequences over Z (Python integers)."""
+    N = len(a)
+    c = [0] * N
+    for i, x in enumerate(a):
+        if x == 0:
+            continue
+        for j, y in enumerate(b):
+            k = i + j
+            if k < N:
+                c[k] += x * y
+            else:
+                c[k - N] -= x * y
+    return c
+
+
+def _crt(res, mods):
+    return int(sympy.ntheory.modular.crt(mods, [int(r) for r in res])[0])
+
+
+@pytest.fixture(scope="module")
+def tiny_mul_oracle(oracle_mod):
+    o = oracle_mod.Oracle(4, 3, 30, 12)  # N = 16, three 30-bit primes
+    o.keygen((5, 6))
+    o.relin_keygen((7, 8))
+    return o
+
+
+def test_special_prime_is_the_next_ntt_prime(oracle_mod, tiny_mul_oracle):
+    o = tiny_mul_oracle
+    four = oracle_mod.gen_primes(o.log_n, 30, 4)
+    assert o.q == four[:3] and o.qP == four[3]
+    assert sympy.isprime(o.qP) and (o.qP - 1) % (2 * o.N) == 0
+    assert pow(o.psiP, o.N, o.qP) == o.qP - 1
+
+
+@pytest.mark.parametrize("level", [3, 2, 1])
+def test_key_switch_decrypts_to_qP_d2_s2_plus_small(tiny_mul_oracle, level):
+    # With s, the key-switched digits decrypt (mod qP * Q_level) exactly to
+    # qP * D2 * s^2 + sum_i d2_i * e_i, where D2 is the CRT value of the digits and e_i
+    # the keys' error streams: the key carries qP s^2 in limb i only, all keys share the
+    # secret, and each digit is lifted as the integer it is.
+    o = tiny_mul_oracle
+    N = o.N
+    rng = np.random.default_rng(level)
+    d2 = np.concatenate([rng.integers(0, q, N, dtype=np.uint64) for q in o.q[:level]])
+    acc = o.key_switch(d2, level).reshape(2, level + 1, N)
+    mods = o.q[:level] + [o.qP]
+    M = math.prod(mods)
+    s = [int(x) for x in o.s]
+    B = [_crt(acc[0, :, c], mods) for c in range(N)]
+    A = [_crt(acc[1, :, c], mods) for c in range(N)]
+    As = _negacyclic_int(A, s)
+    dec = [(B[c] + As[c]) % M for c in range(N)]
+    digits = [[int(x) for x in d2[i * N:(i + 1) * N]] for i in range(level)]
+    D2 = [_crt([digits[i][c] for i in range(level)], o.q[:level]) for c in range(N)]
+    want = [o.qP * v for v in _negacyclic_int(D2, _negacyclic_int(s, s))]
+    for i in range(level):
+        e = [int(x) for x in o.sample_gauss((7, 8), 0, 48 + i)]
+        for c, v in enumerate(_negacyclic_int(digits[i], e)):
+            want[c] += v
+    assert dec == [w % M for w in want]
+
+
+def test_mod_down_is_rounded_division_by_qP(tiny_mul_oracle):
+    o = tiny_mul_oracle
+    N = o.N
+    rng = np.random.default_rng(11)
+    for level in (3, 1):
+        mods = o.q[:level] + [o.qP]
+        acc = np.stack([np.stack([rng.integers(0, m, N, dtype=np.uint64) for m in mods]) for _ in range(2)])
+        out = o.mod_down(acc.reshape(-1), level).reshape(2, level, N)
+        for k in range(2):
+            for c in range(N):
+                x = _crt(acc[k, :, c], mods)
+                r = x % o.qP
+                if r > o.qP // 2:
+                    r -= o.qP
+                y = (x - r) // o.qP  # exact; |y - x/qP| <= 1/2
+                assert abs(y - x / o.qP) <= 0.5 + 1e-9
+                for j in range(level):
+                    assert int(out[k, j, c]) == y % o.q[j]
+
+
+def test_tensor_is_the_product_of_the_decryptions(tiny_mul_oracle):
+    # d0 + d1 s + d2 s^2 = (a0 + a1 s)(b0 + b1 s) in each R_q
+    o = tiny_mul_oracle
+    N, L = o.N, o.L
+    a = o.encrypt(37.0, (1, 1), 3)
+    b = o.encrypt(201.0, (1, 1), 4)
+    d = o.tensor(a, b).reshape(3, L, N)
+    a2, b2 = a.reshape(2, L, N), b.reshape(2, L, N)
+    s = [int(x) for x in o.s]
+    for j, q in enumerate(o.q):
+        lhs = [0] * N
+        for k, poly in enumerate((d[0, j], d[1, j], d[2, j])):
+            term = [int(x) for x in poly]
+            for _ in range(k):
+                term = _negacyclic_int(term, s)
+            lhs = [x + y for x, y in zip(lhs, term)]
+        da = [int(x) + y for x, y in zip(a2[0, j], _negacyclic_int([int(v) for v in a2[1, j]], s))]
+        db = [int(x) + y for x, y in zip(b2[0, j], _negacyclic_int([int(v) for v in b2[1, j]], s))]
+        rhs = _negacyclic_int(da, db)
+        assert [x % q for x in lhs] == [x % q for x in rhs]
+
+
+@pytest.fixture(scope="module")
+def c1_mul_oracle(oracle_mod):
+    o = oracle_mod.Oracle(12, 3, 36, 30)
+    o.keygen((0x240903568, 1))
+    o.relin_keygen((0x240903568, 99))
+    return o
+
+
+def test_product_decrypts_to_the_product_of_pixels(c1_mul_oracle):
+    # CKKS multiplication: (p1 * p2) at scale Delta^2, rescaled once (Sec. 2.2.3)
+    o = c1_mul_oracle
+    for p1, p2 in ((0, 255), (17, 23), (255, 255), (128, 3)):
+        a = o.encrypt(p1, (2, 2), p1)
+        b = o.encrypt(p2, (2, 2), 1000 + p2)
+        m = o.mul(a, b)
+        r, sc = o.rescale(m, level=3, scale=o.scale * o.scale)
+        assert sc == o.scale * o.scale / o.q[2]
+        got = o.decrypt(r, level=2, scale=sc)
+        assert abs(got - p1 * p2) < 0.05, (p1, p2, got)
+
+
+def test_squared_difference_gives_the_l1_distance(c1_mul_oracle):
+    # image matching (Sec. 4.4.3): per pixel (I1 - I2)^2 in encrypted form; the client
+    # decrypts and sums the square roots, which is the L1 distance
+    o = c1_mul_oracle
+    rng = np.random.default_rng(3)
+    i1 = rng.integers(0, 256, 6)
+    i2 = rng.integers(0, 256, 6)
+    total = 0.0
+    for t, (x, y) in enumerate(zip(i1, i2)):
+        d = o.sub(o.encrypt(float(x), (4, 4), t), o.encrypt(float(y), (4, 5), t))
+        sq, sc = o.rescale(o.mul(d, d), level=3, scale=o.scale * o.scale)
+        v = o.decrypt(sq, level=2, scale=sc)
+        assert abs(v - (int(x) - int(y)) ** 2) < 0.05
+        total += math.sqrt(max(v, 0.0))
+    assert abs(total - np.abs(i1.astype(int) - i2.astype(int)).sum()) < 0.05
