@@ -150,13 +150,28 @@ int ckks_context_info(const ckks_ctx *ctx, uint32_t *log_n, uint32_t *num_primes
 
 /* Generate s (ternary), e (Gaussian), a_i (uniform mod q_i) from Philox keyed by seed
  * (counter index 0; tags 16, 17, 32+i) and set pk = (-a*s + e, a), on the GPU.
- * Synchronous: returns after the keys are ready.  No evaluation key is generated
- * (no ciphertext-ciphertext product is implemented). */
+ * Synchronous: returns after the keys are ready.  The key-switching keys of the
+ * ciphertext product are generated separately (ckks_relin_keygen). */
 int ckks_keygen(ckks_ctx *ctx, const uint64_t seed[2]);
 /* Copy the keys out: host_s[N] (int64 in {-1,0,1}), host_pk[2][L][N]. Either may be NULL. */
 int ckks_keys_export(ckks_ctx *ctx, int64_t *host_s, uint64_t *host_pk);
 /* Install keys produced elsewhere (s[N] in {-1,0,1}; pk[2][L][N] canonical residues). */
 int ckks_keys_import(ckks_ctx *ctx, const int64_t *host_s, const uint64_t *host_pk);
+
+/* Key-switching keys of s^2 for relinearization (Sec. 2.2.3, hybrid key switching
+ * with one special prime qP and one digit per limb).  qP is the largest prime
+ * congruent to 1 mod 2N below 2^bits that is not one of the q_i.  Key i (i < L), in
+ * each prime p_j of q_0..q_{L-1}, qP (j = L):
+ *   b_ij = -a_ij * s + e_i + [j == i] (qP mod q_i) s^2 (mod p_j),  a_ij uniform mod p_j,
+ * with e_i Gaussian from Philox (seed, 0, 48 + i) and a_ij by rejection from
+ * (seed, 0, 64 + 32 i + j) as in ckks_keygen.  Requires keys (CKKS_ESTATE);
+ * CKKS_EUNSUPPORTED if no such qP exists.  Synchronous; allocates the keys on first
+ * use (2 * L * (L+1) * 2 * N * 8 bytes with their NTT-domain copies). */
+int ckks_relin_keygen(ckks_ctx *ctx, const uint64_t seed[2]);
+/* Copy the key-switching keys out as host_evk[L][L+1][2][N] (b then a; canonical
+ * residues) and the special prime.  Either pointer may be NULL.  CKKS_ESTATE without
+ * ckks_relin_keygen. */
+int ckks_relin_keys_export(ckks_ctx *ctx, uint64_t *host_evk, uint64_t *host_special_prime);
 
 /* ---- encryption ---- */
 
@@ -209,6 +224,19 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
  * may alias a->data or b->data; out->count/level/scale are set. */
 int ckks_add(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream);
 int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream);
+
+/* Relinearized product out = a * b (Sec. 2.2.3; the squared difference of image
+ * matching, Sec. 4.4.3), ciphertext by ciphertext:
+ *   (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1) in each q_j;
+ *   acc = sum_i d2_i * key_i in q_0..q_{level-1} and qP, d2_i the limb-i residues taken
+ *         as integers in [0, q_i);
+ *   out_k = d_k + (acc_k - [acc_k]_qP) * qP^-1 (mod q_j), [.]_qP the centered residue.
+ * a and b must have the same count and level (CKKS_ELEVEL); scales may differ and
+ * out->scale = a->scale * b->scale at the same level (ckks_rescale brings it back).
+ * Requires ckks_relin_keygen (CKKS_ESTATE).  out->data may equal a->data or b->data;
+ * any other overlap is CKKS_EINVAL.  Uses min(count, 2048) * (level + 2) * N * 8
+ * bytes of temporary device memory (stream-ordered). */
+int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream);
 
 /* out = c * a.  An integer-valued c multiplies exactly and keeps the scale; any other c
  * multiplies by K = rint(c * q_{level-1}) and sets out->scale = a->scale * q_{level-1}, so

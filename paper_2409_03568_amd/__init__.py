@@ -97,6 +97,10 @@ _SIGS = {
     "ckks_keygen": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "ckks_keys_export": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
     "ckks_keys_import": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
+    "ckks_relin_keygen": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "ckks_relin_keys_export": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "ckks_mul": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.POINTER(ckks_ct_batch_t),
+                           C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_encrypt_pixels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_uint64,
                                       C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_cache_build": (C.c_int, [C.c_void_p, C.POINTER(ckks_cache_desc_t), C.c_void_p, C.c_uint64,
@@ -320,6 +324,16 @@ class Context:
         _check(lib().ckks_keys_import(self.handle, s.ctypes.data_as(C.POINTER(C.c_int64)),
                                       pk.ctypes.data_as(C.POINTER(C.c_uint64))))
 
+    def relin_keygen(self, seed):
+        _check(lib().ckks_relin_keygen(self.handle, _seed(seed)))
+
+    def relin_keys_export(self):
+        """(evk[L][L+1][2][N] as uint64, the special prime qP)."""
+        evk = np.zeros(self.L * (self.L + 1) * 2 * self.N, dtype=np.uint64)
+        qP = C.c_uint64(0)
+        _check(lib().ckks_relin_keys_export(self.handle, evk.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(qP)))
+        return evk.reshape(self.L, self.L + 1, 2, self.N), int(qP.value)
+
     # -- encryption -------------------------------------------------------------
     def encrypt_pixels(self, px, seed, first_index: int = 0, out: Ciphertexts | None = None,
                        stream=None) -> Ciphertexts:
@@ -363,6 +377,9 @@ class Context:
 
     def sub(self, a, b, out=None, stream=None) -> Ciphertexts:
         return self._binary(lib().ckks_sub, a, b, out, stream)
+
+    def mul(self, a, b, out=None, stream=None) -> Ciphertexts:
+        return self._binary(lib().ckks_mul, a, b, out, stream)
 
     def mul_const(self, a: Ciphertexts, c: float, out=None, stream=None) -> Ciphertexts:
         out = self.empty(a.count, a.level) if out is None else out

@@ -74,7 +74,7 @@ int resolve_params(const ckks_params *p, host::Resolved *r) {
 
 void free_tables(ckks_ctx *c) {
   DevTables &d = c->dev;
-  void *ptrs[] = {d.tw_fwd, d.tw_inv, d.enc_T, d.cosj, d.cdt, d.s, d.pk, d.pk_hat, d.s_hat, c->d_lc};
+  void *ptrs[] = {d.tw_fwd, d.tw_inv, d.enc_T, d.cosj, d.cdt, d.s, d.pk, d.pk_hat, d.s_hat, d.evk, d.evk_hat, c->d_lc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevTables{};
@@ -240,20 +240,26 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   lc.L = L;
   lc.B = r.B;
   double qmax = 0;
-  std::vector<double> twf((size_t)L * N), twi((size_t)L * N);
-  for (int i = 0; i < L; i++) {
-    const uint64_t q = r.q[(size_t)i];
+  // rows 0..L-1: the ciphertext primes; row L: the special prime of key switching (if any)
+  const int rows = L + (r.qP ? 1 : 0);
+  std::vector<double> twf((size_t)rows * N), twi((size_t)rows * N);
+  for (int i = 0; i < rows; i++) {
+    const uint64_t q = i < L ? r.q[(size_t)i] : r.qP;
     lc.q[i] = (double)q;
     lc.qinv[i] = 1.0 / (double)q;
     lc.qi[i] = q;
     const uint64_t ni = host::inv_mod((uint64_t)N % q, q);
-    c->ninv.push_back(ni);
+    if (i < L) c->ninv.push_back(ni);
     lc.ninv[i] = host::centered(ni, q);
     qmax = std::max(qmax, (double)q);
     std::vector<double> f, iv;
-    host::twiddles(q, r.psi[(size_t)i], r.log_n, f, iv);
+    host::twiddles(q, i < L ? r.psi[(size_t)i] : r.psiP, r.log_n, f, iv);
     std::copy(f.begin(), f.end(), twf.begin() + (size_t)i * N);
     std::copy(iv.begin(), iv.end(), twi.begin() + (size_t)i * N);
+    if (i < L && r.qP) {
+      lc.pinv[i] = host::centered(host::inv_mod(r.qP % q, q), q);
+      lc.pmod[i] = host::centered(r.qP % q, q);
+    }
   }
   // the transforms' lazy-reduction schedule is compiled per class of prime sizes
   c->rc = qmax < 1099511627776.0 ? 0 : 1;
@@ -264,8 +270,8 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   c->logr_dec = 4;
   hipError_t e = hipSuccess;
   DevTables &d = c->dev;
-  if (e == hipSuccess) e = dev_alloc(&d.tw_fwd, (size_t)L * N);
-  if (e == hipSuccess) e = dev_alloc(&d.tw_inv, (size_t)L * N);
+  if (e == hipSuccess) e = dev_alloc(&d.tw_fwd, (size_t)rows * N);
+  if (e == hipSuccess) e = dev_alloc(&d.tw_inv, (size_t)rows * N);
   if (e == hipSuccess) e = dev_alloc(&d.enc_T, (size_t)N);
   if (e == hipSuccess) e = dev_alloc(&d.cosj, (size_t)N);
   if (e == hipSuccess) e = dev_alloc(&d.cdt, (size_t)kCdtSlots);
@@ -371,6 +377,37 @@ int ckks_keys_export(ckks_ctx *ctx, int64_t *host_s, uint64_t *host_pk) {
   const size_t N = (size_t)ctx->N, L = (size_t)ctx->prm.L;
   if (host_s) HIP_TRY(hipMemcpy(host_s, ctx->dev.s, N * sizeof(int64_t), hipMemcpyDeviceToHost), "export s");
   if (host_pk) HIP_TRY(hipMemcpy(host_pk, ctx->dev.pk, 2 * L * N * sizeof(uint64_t), hipMemcpyDeviceToHost), "export pk");
+  return CKKS_OK;
+}
+
+int ckks_relin_keygen(ckks_ctx *ctx, const uint64_t seed[2]) {
+  int rc = check_keys(ctx);
+  if (rc) return rc;
+  if (!seed) return fail(CKKS_EINVAL, "seed is NULL");
+  if (!ctx->prm.qP) return fail(CKKS_EUNSUPPORTED, "no special prime of the NTT form exists for these parameters");
+  DeviceGuard g(ctx->device);
+  const size_t words = (size_t)ctx->prm.L * (ctx->prm.L + 1) * 2 * ctx->N;
+  if (!ctx->dev.evk) {
+    if (dev_alloc(&ctx->dev.evk, words) != hipSuccess) return fail(CKKS_ENOMEM, "key-switching key allocation");
+    if (dev_alloc(&ctx->dev.evk_hat, words) != hipSuccess) return fail(CKKS_ENOMEM, "key-switching key allocation");
+  }
+  ctx->has_relin = false;
+  HIP_TRY(launch_relin_keygen(ctx, seed[0], seed[1], nullptr), "key-switching keygen launch");
+  HIP_TRY(launch_relin_prepare(ctx, nullptr), "key-switching key preparation launch");
+  HIP_TRY(hipDeviceSynchronize(), "key-switching keygen");
+  ctx->has_relin = true;
+  return CKKS_OK;
+}
+
+int ckks_relin_keys_export(ckks_ctx *ctx, uint64_t *host_evk, uint64_t *host_special_prime) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!ctx->has_relin) return fail(CKKS_ESTATE, "no key-switching keys: call ckks_relin_keygen first");
+  if (host_special_prime) *host_special_prime = ctx->prm.qP;
+  if (!host_evk) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  const size_t words = (size_t)ctx->prm.L * (ctx->prm.L + 1) * 2 * ctx->N;
+  HIP_TRY(hipMemcpy(host_evk, ctx->dev.evk, words * sizeof(uint64_t), hipMemcpyDeviceToHost), "export evk");
   return CKKS_OK;
 }
 
@@ -602,6 +639,10 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
   return CKKS_OK;
 }
 
+static bool overlaps(const uint64_t *a, uint64_t an, const uint64_t *b, uint64_t bn) {
+  return a < b + bn && b < a + an;
+}
+
 static int binary_common(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
@@ -640,6 +681,38 @@ int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
   return CKKS_OK;
 }
 
+int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if ((rc = check_batch(ctx, a, "a")) || (rc = check_batch(ctx, b, "b"))) return rc;
+  if (!ctx->has_relin) return fail(CKKS_ESTATE, "no key-switching keys: call ckks_relin_keygen first");
+  if (!out) return fail(CKKS_EINVAL, "out is NULL");
+  if (a->count != b->count) return fail(CKKS_EINVAL, "counts differ (%llu vs %llu)", (unsigned long long)a->count, (unsigned long long)b->count);
+  if (a->level != b->level) return fail(CKKS_ELEVEL, "levels differ (%u vs %u)", a->level, b->level);
+  const double ns = a->scale * b->scale;
+  if (!isfinite(ns)) return fail(CKKS_ESCALE, "product scale overflows");
+  if (a->count && !out->data) return fail(CKKS_EINVAL, "out data is NULL");
+  const uint64_t words = a->count * ct_words(ctx, a->level);
+  for (const ckks_ct_batch *in : {a, b})
+    if (a->count && in->data != out->data && overlaps(in->data, words, out->data, words))
+      return fail(CKKS_EINVAL, "product output overlaps an input other than exactly");
+  const ckks_ct_batch av = *a;
+  const uint64_t *bd = b->data;
+  out->count = av.count;
+  out->level = av.level;
+  out->scale = ns;
+  if (!av.count) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  void *ws = nullptr;
+  HIP_TRY(hipMallocFromPoolAsync(&ws, mul_scratch_words(av.count, (int)av.level, ctx->N) * sizeof(uint64_t), ctx->pool,
+                                 st),
+          "workspace alloc");
+  HIP_TRY(launch_mul(ctx, av.data, bd, out->data, av.count, (int)av.level, static_cast<uint64_t *>(ws), st), "mul");
+  HIP_TRY(hipFreeAsync(ws, st), "workspace free");
+  return CKKS_OK;
+}
+
 int ckks_mul_const(ckks_ctx *ctx, const ckks_ct_batch *a, double c, ckks_ct_batch *out, void *stream) {
   int rc = check_ctx(ctx);
   if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
@@ -665,10 +738,6 @@ int ckks_add_const(ckks_ctx *ctx, ckks_ct_batch *a, const double *d_b, double b,
   DeviceGuard g(ctx->device);
   HIP_TRY(launch_add_const(ctx, a->data, a->count, (int)a->level, a->scale, d_b, b, as_stream(stream)), "add_const");
   return CKKS_OK;
-}
-
-static bool overlaps(const uint64_t *a, uint64_t an, const uint64_t *b, uint64_t bn) {
-  return a < b + bn && b < a + an;
 }
 
 int ckks_rescale(ckks_ctx *ctx, const ckks_ct_batch *a, ckks_ct_batch *out, void *stream) {

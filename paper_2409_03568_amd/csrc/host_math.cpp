@@ -127,6 +127,16 @@ std::string resolve(uint32_t log_n, uint32_t L, uint32_t bits, uint32_t log_scal
     if (!psi) return "no primitive root found";
     out->psi.push_back(psi);
   }
+  out->qP = 0;
+  out->psiP = 0;
+  {
+    const uint64_t lo = 1ULL << (bits - 1);
+    for (uint64_t c = (((1ULL << bits) - 2) / twoN) * twoN + 1; c > lo && !out->qP; c -= twoN) {
+      if (std::find(q.begin(), q.end(), c) == q.end() && is_prime(c)) out->qP = c;
+    }
+    if (out->qP) out->psiP = find_psi(out->qP, (int)log_n);
+    if (!out->psiP) out->qP = 0;
+  }
   *code = CKKS_OK;
   return "";
 }

@@ -20,6 +20,10 @@ struct Resolved {
   int B = 0;
   std::vector<uint64_t> q;    // descending
   std::vector<uint64_t> psi;  // primitive 2N-th roots
+  // special prime of key switching (ciphertext multiplication): the largest prime with
+  // prime_bits bits, = 1 mod 2N, that is not one of q; 0 if there is none
+  uint64_t qP = 0;
+  uint64_t psiP = 0;
 };
 
 // Returns an empty string on success, else the reason (and sets *code to a CKKS_E* value).

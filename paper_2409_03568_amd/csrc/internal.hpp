@@ -16,20 +16,23 @@ namespace ckks {
 constexpr int kMaxL = 16;
 constexpr int kMaxDigits = 8;
 
-// Per-limb constants; kernels read the device copy held by the context.
+// Per-limb constants; kernels read the device copy held by the context.  Index L holds
+// the special prime of key switching (when the context has one).
 struct LimbConsts {
   int L;                 // limbs of the context
   int B;                 // Gaussian bound (0 = no noise)
-  double q[kMaxL];
-  double qinv[kMaxL];
-  double ninv[kMaxL];    // N^-1 mod q_i, centered
-  uint64_t qi[kMaxL];
+  double q[kMaxL + 1];
+  double qinv[kMaxL + 1];
+  double ninv[kMaxL + 1];    // N^-1 mod q_i, centered
+  uint64_t qi[kMaxL + 1];
+  double pinv[kMaxL];        // qP^-1 mod q_i, centered (ModDown)
+  double pmod[kMaxL];        // qP mod q_i, centered (the s^2 term of key-switching key i)
 };
 
 // Device tables owned by a context.
 struct DevTables {
-  double *tw_fwd = nullptr;  // [L][N]
-  double *tw_inv = nullptr;  // [L][N]
+  double *tw_fwd = nullptr;  // [L+1][N] (row L: the special prime)
+  double *tw_inv = nullptr;  // [L+1][N]
   double *enc_T = nullptr;   // [N] encoding table at scale Delta
   double *cosj = nullptr;    // [N] cos(pi j / N)
   uint64_t *cdt = nullptr;   // [kCdtSlots]
@@ -37,6 +40,8 @@ struct DevTables {
   uint64_t *pk = nullptr;    // [2][L][N] public key, coefficient domain
   double *pk_hat = nullptr;  // [2][L][N] NTT domain times N^-1, centered
   double *s_hat = nullptr;   // [L][N] NTT domain times N^-1, centered
+  uint64_t *evk = nullptr;   // [L][L+1][2][N] key-switching keys of s^2, coefficient domain
+  double *evk_hat = nullptr; // [L][L+1][2][N] the same in the NTT domain times N^-1, centered
 };
 
 // What to encrypt, in one of three forms (the launcher picks the kernel variant):
@@ -92,6 +97,7 @@ struct ckks_ctx {
   ckks::DevTables dev{};
   std::vector<uint64_t> ninv;  // N^-1 mod q_i
   bool has_keys = false;
+  bool has_relin = false;      // key-switching keys of s^2 generated
   hipStream_t pipe[3] = {nullptr, nullptr, nullptr};  // image pipeline stages, created on first use
   hipMemPool_t pool = nullptr;  // stream-ordered scratch that keeps its memory between calls
 };
@@ -133,6 +139,17 @@ hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream);
 hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream);
 hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
                           hipStream_t stream);
+// Key-switching keys of s^2 (grid: digits x primes), then their NTT-domain copies.
+hipError_t launch_relin_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
+hipError_t launch_relin_prepare(const ckks_ctx *c, hipStream_t stream);
+// Relinearized products out = a * b of n ciphertext pairs at `level`; the kernel runs
+// min(n, kMulGroups) workgroups and scratch holds (level + 2) * N words for each.
+constexpr uint64_t kMulGroups = 2048;
+inline uint64_t mul_scratch_words(uint64_t n, int level, int N) {
+  return (n < kMulGroups ? n : kMulGroups) * (uint64_t)(level + 2) * (uint64_t)N;
+}
+hipError_t launch_mul(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n, int level,
+                      uint64_t *scratch, hipStream_t stream);
 
 hipError_t launch_add_sub(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
                           int level, bool sub, hipStream_t stream);

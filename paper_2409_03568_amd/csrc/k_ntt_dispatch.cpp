@@ -7,7 +7,11 @@ namespace ckks {
   hipError_t launch_encrypt_##LOGN(const ckks_ctx *, const EncJob &, uint64_t, hipStream_t);                 \
   hipError_t launch_keygen_##LOGN(const ckks_ctx *, uint64_t, uint64_t, hipStream_t);                        \
   hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *, hipStream_t);                                      \
-  hipError_t launch_decrypt_##LOGN(const ckks_ctx *, const uint64_t *, uint64_t, int, double, double *, hipStream_t);
+  hipError_t launch_decrypt_##LOGN(const ckks_ctx *, const uint64_t *, uint64_t, int, double, double *, hipStream_t); \
+  hipError_t launch_relin_keygen_##LOGN(const ckks_ctx *, uint64_t, uint64_t, hipStream_t);                  \
+  hipError_t launch_relin_prepare_##LOGN(const ckks_ctx *, hipStream_t);                                     \
+  hipError_t launch_mul_##LOGN(const ckks_ctx *, const uint64_t *, const uint64_t *, uint64_t *, uint64_t, int, \
+                               uint64_t *, hipStream_t);
 CKKS_DECLARE_RING(11)
 CKKS_DECLARE_RING(12)
 CKKS_DECLARE_RING(13)
@@ -32,6 +36,14 @@ hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream) { CKKS_RIN
 hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
                           hipStream_t stream) {
   CKKS_RING_SWITCH(launch_decrypt, cts, n, level, scale, out, stream)
+}
+hipError_t launch_relin_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream) {
+  CKKS_RING_SWITCH(launch_relin_keygen, seed0, seed1, stream)
+}
+hipError_t launch_relin_prepare(const ckks_ctx *c, hipStream_t stream) { CKKS_RING_SWITCH(launch_relin_prepare, stream) }
+hipError_t launch_mul(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n, int level,
+                      uint64_t *scratch, hipStream_t stream) {
+  CKKS_RING_SWITCH(launch_mul, a, b, out, n, level, scratch, stream)
 }
 
 }  // namespace ckks

@@ -251,6 +251,217 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 }
 
 // ---------------------------------------------------------------------------
+// key-switching keys of s^2 for ciphertext multiplication (Sec. 2.2.3), one workgroup
+// per (digit i, prime j); prime j = L is the special prime qP.  Key i in prime j:
+//   b = -a * s + e_i + [j == i] (qP mod q_i) s^2,  a uniform mod p_j
+// with e_i the Gaussian stream (seed, 0, 48 + i) and a the uniform stream
+// (seed, 0, 64 + 32 i + j), both as in the key generation above.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTagRkE0 = 48, kTagRkA0 = 64;
+
+template <int LOGN, int LOGR, int RC>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_relin_keygen(uint64_t k0, uint64_t k1, const LimbConsts *__restrict__ lcp, DevTables dt) {
+  using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  const LimbConsts &lc = *lcp;
+  extern __shared__ double lds[];
+  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
+  uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
+  __syncthreads();
+  const int L = lc.L, B = lc.B, i = blockIdx.x, j = blockIdx.y;
+  const double q = lc.q[j], qinv = lc.qinv[j];
+  const uint64_t qi = lc.qi[j];
+  const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
+  uint32_t smp[R];
+  const uint32_t etag = kTagRkE0 + (uint32_t)i;
+  draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, tid, k0, k1, 0, etag, etag, etag);
+  const uint64_t limit = 0ULL - ((~0ULL % qi + 1) % qi);
+  uint64_t *kb = dt.evk + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
+  double a[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const uint32_t c = (uint32_t)(tid + T * r);
+    uint64_t val = 0;
+    bool done = false;
+    for (uint64_t att = 0; !done; att++) {
+      const Philox4 w = philox4x64_10(0, kTagRkA0 + 32u * (uint32_t)i + (uint32_t)j, att * N + c, 0, k0, k1);
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (!done && w.w[k] < limit) {
+          val = w.w[k] % qi;
+          done = true;
+        }
+      }
+    }
+    ka[c] = val;
+    a[r] = (double)val;
+  }
+  // s_hat and s_hat * N^-1 in this prime
+  double sh[R], shn[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) sh[r] = (double)dt.s[tid + T * r];
+  ntt_forward<LOGN, LOGR, Red::fwd_small>(sh, lds, tid, tw, q, qinv);
+  const double ninv = lc.ninv[j];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    sh[r] = reduce(sh[r], q, qinv);
+    shn[r] = reduce(mulmod(sh[r], ninv, q, qinv), q, qinv);
+  }
+  ntt_forward<LOGN, LOGR, Red::fwd_big>(a, lds, tid, tw, q, qinv);
+  const bool own = (j == i);
+  const double pm = own ? lc.pmod[i] : 0.0;
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    double v = -mulmod(a[r], shn[r], q, qinv);
+    if (own) v += mulmod(mulmod(sh[r], shn[r], q, qinv), pm, q, qinv);
+    a[r] = reduce(v, q, qinv);
+  }
+  ntt_inverse<LOGN, LOGR, Red::inv>(a, lds, tid, itw, q, qinv);
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const double e = (double)smp_g(smp[r], 8, B);
+    kb[tid + T * r] = (uint64_t)canon(a[r] + e, q, qinv);
+  }
+}
+
+// NTT-domain copies of the key-switching keys times N^-1 (grid: digits x primes x 2).
+template <int LOGN, int LOGR, int RC>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_relin_prepare(const LimbConsts *__restrict__ lcp, DevTables dt) {
+  using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  const LimbConsts &lc = *lcp;
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, i = blockIdx.x, j = blockIdx.y, k = blockIdx.z, L = lc.L;
+  const double q = lc.q[j], qinv = lc.qinv[j];
+  const size_t off = ((((size_t)i * (L + 1) + j) * 2) + k) * N;
+  double x[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) x[r] = u64_to_f64(dt.evk[off + tid + T * r]);
+  ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd + (size_t)j * N, q, qinv);
+#pragma unroll
+  for (int r = 0; r < R; r++)
+    dt.evk_hat[off + elem_index<LOGN, LOGR, S::LAST>(tid, r)] = reduce(mulmod(x[r], lc.ninv[j], q, qinv), q, qinv);
+}
+
+// ---------------------------------------------------------------------------
+// relinearized product of ciphertext pairs (Sec. 2.2.3), one workgroup per pair:
+//  1. per limb j: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 through the NTT; d0, d1
+//     go to the output, d2 (coefficient domain) to scratch;
+//  2. key switching of d2, prime by prime (the special prime first): for every digit
+//     i (= d2 limb i as an integer below q_i), lift to the prime, transform, and
+//     accumulate its products with key i; back to coefficients;
+//  3. ModDown: out_k = d_k + (acc_k - [acc_k]_qP) qP^-1 mod q_j, [.]_qP centered.
+// All arithmetic exact FP64 on signed representatives kept inside the transform bounds.
+// ---------------------------------------------------------------------------
+template <int LOGN, int LOGR, int RC>
+__global__ void __launch_bounds__(1 << (LOGN - LOGR))
+    k_mul(const uint64_t *__restrict__ A, const uint64_t *__restrict__ Bc, uint64_t *__restrict__ out, uint64_t n,
+          int level, uint64_t *__restrict__ scratch, const LimbConsts *__restrict__ lcp, DevTables dt) {
+  using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  const LimbConsts &lc = *lcp;
+  extern __shared__ double lds[];
+  const int L = lc.L;
+  const uint64_t S_ct = (uint64_t)2 * level * N;
+  // scratch of this workgroup: d2 [level][N] words, then the centered special-prime
+  // accumulators [2][N] doubles; every element is written and read by the same thread
+  uint64_t *d2s = scratch + (uint64_t)blockIdx.x * (uint64_t)(level + 2) * N;
+  double *accP = reinterpret_cast<double *>(d2s + (size_t)level * N);
+  for (uint64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const uint64_t *a = A + it * S_ct, *b = Bc + it * S_ct;
+    uint64_t *o = out + it * S_ct;
+    // 1. tensor product, limb by limb
+    for (int j = 0; j < level; j++) {
+      const int tid = opaque(threadIdx.x);
+      const double q = lc.q[j], qinv = lc.qinv[j], ninv = lc.ninv[j];
+      const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
+      double x0[R], x1[R], y0[R], y1[R];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        x0[r] = u64_to_f64(a[(size_t)j * N + tid + T * r]);
+        x1[r] = u64_to_f64(a[((size_t)level + j) * N + tid + T * r]);
+        y0[r] = u64_to_f64(b[(size_t)j * N + tid + T * r]);
+        y1[r] = u64_to_f64(b[((size_t)level + j) * N + tid + T * r]);
+      }
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(x0, lds, tid, tw, q, qinv);
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(x1, lds, tid, tw, q, qinv);
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(y0, lds, tid, tw, q, qinv);
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(y1, lds, tid, tw, q, qinv);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        // the a side carries N^-1; every product has operands below q
+        const double a0 = reduce(mulmod(x0[r], ninv, q, qinv), q, qinv);
+        const double a1 = reduce(mulmod(x1[r], ninv, q, qinv), q, qinv);
+        const double b0 = reduce(y0[r], q, qinv), b1 = reduce(y1[r], q, qinv);
+        x0[r] = mulmod(a0, b0, q, qinv);
+        x1[r] = reduce(mulmod(a0, b1, q, qinv) + mulmod(a1, b0, q, qinv), q, qinv);
+        y0[r] = mulmod(a1, b1, q, qinv);
+      }
+      ntt_inverse<LOGN, LOGR, Red::inv>(x0, lds, tid, itw, q, qinv);
+      ntt_inverse<LOGN, LOGR, Red::inv>(x1, lds, tid, itw, q, qinv);
+      ntt_inverse<LOGN, LOGR, Red::inv>(y0, lds, tid, itw, q, qinv);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int c = tid + T * r;
+        o[(size_t)j * N + c] = f64_to_u64(canon(x0[r], q, qinv));
+        o[((size_t)level + j) * N + c] = f64_to_u64(canon(x1[r], q, qinv));
+        d2s[(size_t)j * N + c] = f64_to_u64(canon(y0[r], q, qinv));
+      }
+    }
+    // 2 + 3. key switching, the special prime (index L) first
+    for (int jj = 0; jj <= level; jj++) {
+      const int tid = opaque(threadIdx.x);
+      const int j = jj == 0 ? L : jj - 1;
+      const double q = lc.q[j], qinv = lc.qinv[j];
+      const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
+      double c0[R], c1[R];
+#pragma unroll
+      for (int r = 0; r < R; r++) c0[r] = c1[r] = 0.0;
+      for (int i = 0; i < level; i++) {
+        double x[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) x[r] = reduce(u64_to_f64(d2s[(size_t)i * N + tid + T * r]), q, qinv);
+        ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, tw, q, qinv);
+        const double *kb = dt.evk_hat + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const unsigned e = elem_index<LOGN, LOGR, S::LAST>(tid, r);
+          c0[r] = reduce(c0[r] + mulmod(x[r], kb[e], q, qinv), q, qinv);
+          c1[r] = reduce(c1[r] + mulmod(x[r], ka[e], q, qinv), q, qinv);
+        }
+      }
+      ntt_inverse<LOGN, LOGR, Red::inv>(c0, lds, tid, itw, q, qinv);
+      ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
+      if (jj == 0) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          accP[tid + T * r] = center(c0[r], q, qinv);
+          accP[N + tid + T * r] = center(c1[r], q, qinv);
+        }
+        continue;
+      }
+      const double pinv = lc.pinv[j];
+      const uint64_t qi = lc.qi[j];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int c = tid + T * r;
+        const double m0 = canon(mulmod(canon(c0[r], q, qinv) - accP[c], pinv, q, qinv), q, qinv);
+        const double m1 = canon(mulmod(canon(c1[r], q, qinv) - accP[N + c], pinv, q, qinv), q, qinv);
+        o[(size_t)j * N + c] = add_mod(o[(size_t)j * N + c], f64_to_u64(m0), qi);
+        o[((size_t)level + j) * N + c] = add_mod(o[((size_t)level + j) * N + c], f64_to_u64(m1), qi);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // decryption of limb 0 and decoding of slot 0:
 //   d = c0 + INTT(NTT(c1) * s_hat); out = sum_j center(d_j) cos(pi j/N) / scale
 // ---------------------------------------------------------------------------
@@ -360,6 +571,29 @@ struct Launch {
     hipLaunchKernelGGL((k_keys_prepare<LOGN, LOGR, RC>), dim3(c->lc.L, 3), dim3(S::T), S::lds_bytes, st, c->d_lc, c->dev);
     return hipGetLastError();
   }
+  static hipError_t relin_keygen(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR, k_relin_keygen<LOGN, LOGR, RC>>();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relin_keygen<LOGN, LOGR, RC>), dim3(c->lc.L, c->lc.L + 1), dim3(S::T), S::lds_bytes, st, s0,
+                       s1, c->d_lc, c->dev);
+    return hipGetLastError();
+  }
+  static hipError_t relin_prepare(const ckks_ctx *c, hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR, k_relin_prepare<LOGN, LOGR, RC>>();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relin_prepare<LOGN, LOGR, RC>), dim3(c->lc.L, c->lc.L + 1, 2), dim3(S::T), S::lds_bytes, st,
+                       c->d_lc, c->dev);
+    return hipGetLastError();
+  }
+  static hipError_t mul(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n, int level,
+                        uint64_t *scratch, hipStream_t st) {
+    hipError_t e = set_lds<LOGN, LOGR, k_mul<LOGN, LOGR, RC>>();
+    if (e != hipSuccess) return e;
+    const uint64_t grid = n < kMulGroups ? n : kMulGroups;
+    hipLaunchKernelGGL((k_mul<LOGN, LOGR, RC>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, a, b, out, n, level,
+                       scratch, c->d_lc, c->dev);
+    return hipGetLastError();
+  }
   static hipError_t decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
                             hipStream_t st) {
     hipError_t e = set_lds<LOGN, LOGR, k_decrypt<LOGN, LOGR, RC>>();
@@ -373,6 +607,9 @@ struct Launch {
 
 // All launchers of one ring degree, selecting the thread shape (c->logr) and the
 // reduction class (c->rc) at run time.
+// Register blocking of the multiplication kernels (16 values per thread at every N).
+constexpr int kMulLogR = 4;
+
 template <int LOGN>
 struct RingLaunch {
   template <typename F>
@@ -399,6 +636,17 @@ struct RingLaunch {
   }                                                                                                                 \
   hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *c, hipStream_t st) {                                        \
     return RingLaunch<LOGN>::pick(c, c->logr_enc, [&](auto L) { return decltype(L)::prepare(c, st); });             \
+  }                                                                                                                 \
+  hipError_t launch_relin_keygen_##LOGN(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {              \
+    return RingLaunch<LOGN>::pick(c, kMulLogR, [&](auto L) { return decltype(L)::relin_keygen(c, s0, s1, st); });   \
+  }                                                                                                                 \
+  hipError_t launch_relin_prepare_##LOGN(const ckks_ctx *c, hipStream_t st) {                                       \
+    return RingLaunch<LOGN>::pick(c, kMulLogR, [&](auto L) { return decltype(L)::relin_prepare(c, st); });          \
+  }                                                                                                                 \
+  hipError_t launch_mul_##LOGN(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,  \
+                               int level, uint64_t *scratch, hipStream_t st) {                                      \
+    return RingLaunch<LOGN>::pick(                                                                                  \
+        c, kMulLogR, [&](auto L) { return decltype(L)::mul(c, a, b, out, n, level, scratch, st); });                \
   }                                                                                                                 \
   hipError_t launch_decrypt_##LOGN(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale,     \
                                    double *out, hipStream_t st) {                                                   \

@@ -97,6 +97,15 @@ def batched_rgb_images(seed: int = 3, count: int = 64, lo: int = 32, hi: int = 5
     return imgs, b
 
 
+def matching_pair(seed: int, H: int, W: int, sigma: float = 8.0, s: float = 1.1):
+    """A Zipf image and a perturbed copy of it (Gaussian pixel noise, clipped to 0..255)
+    for the squared-difference image match."""
+    rng = np.random.default_rng(seed)
+    a = rng.choice(256, size=(H, W), p=zipf_pmf(s)).astype(np.int64)
+    b = np.clip(a + np.rint(rng.normal(0.0, sigma, size=(H, W))).astype(np.int64), 0, 255)
+    return a.astype(np.uint8), b.astype(np.uint8)
+
+
 def serving_jobs(seed: int, count: int, lo: int = 32, hi: int = 384):
     """Unit-rate exponential arrival gaps and grayscale Zipf images with log-uniform sides;
     the arrival times at rate qps are cumsum(gaps) / qps, so every rate sees the same jobs."""
