@@ -67,6 +67,8 @@ def parse():
                     help="timed runs of the 64-image batched workload (0 = skip it)")
     ap.add_argument("--pipeline-runs", type=int, default=5,
                     help="timed runs per variant of the streamed 512x512 pipeline (0 = skip it)")
+    ap.add_argument("--matching-runs", type=int, default=5,
+                    help="timed runs of the squared-difference image match (0 = skip)")
     ap.add_argument("--serving-jobs", type=int, default=200,
                     help="jobs per load point of the serving measurement (0 = skip it)")
     ap.add_argument("--serving-budget-gb", type=float, default=160.0, help="device bytes the server may hold")
@@ -81,6 +83,91 @@ def ntt_ops_per_ct(log_n, L):
     butterflies = L * 3 * (N // 2) * log_n
     pointwise = 2 * L * N
     return 8 * butterflies + 6 * pointwise
+
+
+def mul_ops_per_pair(log_n, level):
+    """Algorithmic FP64 VALU operations of one relinearized product at `level` limbs:
+    5 transforms per limb for the tensor product (4 forward, 1 inverse for d2), in the
+    special prime level forward and 2 inverse transforms, in each q_j level - 1 forward
+    (digit j's transform comes from the tensor step) and 2 inverse transforms (8 ops per
+    butterfly); per element 7 pointwise products per limb (tensor), 2 per digit and
+    prime (key switching) and 4 per limb (ModDown), 6 ops each."""
+    N = 1 << log_n
+    transforms = 5 * level + (level + 2) + level * (level + 1)
+    products = 7 * level + 2 * level * (level + 1) + 4 * level
+    return 8 * transforms * (N // 2) * log_n + 6 * products * N
+
+
+def matching_bench(P, W, runs):
+    """Image matching by squared differences (Sec. 4.4.3) on two 256x256 images at
+    N = 8192, 4 x 50-bit primes: subtraction, relinearized product, rescale and
+    decryption of every pixel pair; the client-side square roots and sum give the L1
+    distance, checked against the plaintext one."""
+    import torch
+
+    cfg = 2
+    c = W.CONFIGS[cfg]
+    a_img, b_img = W.matching_pair(cfg, 256, 256)
+    n = a_img.size
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale, device=0)
+    ctx.keygen(W.keygen_seed(cfg))
+    ctx.relin_keygen((W.keygen_seed(cfg)[0] ^ 0x5E1, cfg))
+    tune = ctx.autotune(8192)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        a = ctx.encrypt_pixels(torch.from_numpy(a_img.reshape(-1)).cuda(), W.job_seed(cfg, 0), stream=stream)
+        b = ctx.encrypt_pixels(torch.from_numpy(b_img.reshape(-1)).cuda(), W.job_seed(cfg, 1), stream=stream)
+        d = ctx.empty(n)
+        sq = ctx.empty(n)
+        r = ctx.empty(n, c.num_primes - 1)
+        dec = torch.empty(n, dtype=torch.float64, device="cuda")
+
+        def once(ev=None):
+            if ev is not None:
+                ev[0].record(stream)
+            ctx.sub(a, b, out=d, stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+            ctx.mul(d, d, out=sq, stream=stream)
+            if ev is not None:
+                ev[2].record(stream)
+            ctx.rescale(sq, out=r, stream=stream)
+            if ev is not None:
+                ev[3].record(stream)
+            ctx.decrypt_pixels(r, out=dec, stream=stream)
+            if ev is not None:
+                ev[4].record(stream)
+
+        once()
+        stream.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(runs)]
+        for k in range(runs):
+            once(evs[k])
+        stream.synchronize()
+    names = ["sub", "mul", "rescale", "decrypt"]
+    ms = {nm: float(np.median([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(runs)]))
+          for i, nm in enumerate(names)}
+    total = float(np.median([evs[k][0].elapsed_time(evs[k][4]) for k in range(runs)]))
+    got = dec.cpu().numpy()
+    diff = a_img.astype(np.int64).reshape(-1) - b_img.astype(np.int64).reshape(-1)
+    l1 = float(np.sqrt(np.rint(got).clip(0)).sum())
+    best = tune["mul_width"]
+    ops = mul_ops_per_pair(c.log_n, c.num_primes) * n
+    ach = ops / (ms["mul"] / 1e3) / 1e12
+    res = {"pairs": int(n), "ms": {k: round(v, 3) for k, v in ms.items()}, "total_ms": round(total, 3),
+           "pairs_per_s": round(n / (total / 1e3)),
+           "autotune_8192_pairs_ms": {w: {str(k): round(v, 3) for k, v in tune[w + "_ms"].items()}
+                                      for w in ("encrypt", "decrypt", "mul")},
+           "mul_roofline": {"bound": "alu", "kernel": "k_mul<13, %d, 1> (tensor, key switch, ModDown; %d values "
+                                                      "per thread)" % (best.bit_length() - 1, best),
+                            "achieved": round(ach, 3), "peak": round(PEAK_VALU_OPS / 1e12, 3),
+                            "unit": "TVALUop/s (FP64)", "frac": round(ach * 1e12 / PEAK_VALU_OPS, 4)},
+           "max_sq_err": float(np.max(np.abs(got - diff.astype(np.float64) ** 2))),
+           "l1": l1, "l1_plain": float(np.abs(diff).sum())}
+    ctx.close()
+    del a, b, d, sq, r, dec
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(cfg, img, sample):
@@ -469,6 +556,8 @@ def main():
         out["batched"] = batched_bench(P, W, args.batched_runs)
     if args.pipeline_runs > 0:
         out["pipeline"] = pipeline_bench(P, W, args.pipeline_runs)
+    if args.matching_runs > 0:
+        out["matching"] = matching_bench(P, W, args.matching_runs)
     if args.serving_jobs > 0:
         out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb)
     if args.cpu_sample > 0:

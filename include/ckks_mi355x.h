@@ -234,7 +234,7 @@ int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
  * a and b must have the same count and level (CKKS_ELEVEL); scales may differ and
  * out->scale = a->scale * b->scale at the same level (ckks_rescale brings it back).
  * Requires ckks_relin_keygen (CKKS_ESTATE).  out->data may equal a->data or b->data;
- * any other overlap is CKKS_EINVAL.  Uses min(count, 2048) * (level + 2) * N * 8
+ * any other overlap is CKKS_EINVAL.  Uses min(count, 2048) * (2 level + 2) * N * 8
  * bytes of temporary device memory (stream-ordered). */
 int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream);
 
@@ -282,14 +282,17 @@ int ckks_stream_sync(ckks_ctx *ctx, void *stream);
  * Times the NTT kernels (encryption, Sec. 2.2.2: one forward and two inverse
  * transforms per limb; decryption: one forward and one inverse on limb 0) at each
  * supported register blocking (8, 16 or 32 values per thread) on trial_cts synthetic
- * ciphertexts, keeps the faster width for each kernel on this context, and reports the
- * timings.  The choice changes speed only, never results.  Enqueues on the null stream
- * and synchronizes; allocates and frees its own scratch buffers.
+ * ciphertexts, and, once ckks_relin_keygen has run, the relinearized product
+ * (Sec. 2.2.3) of trial_cts pairs; keeps the fastest width for each kernel on this
+ * context and reports the timings.  The choice changes speed only, never results.
+ * Enqueues on the null stream and synchronizes; allocates and frees its own scratch
+ * buffers.
  */
 typedef struct {
   uint32_t encrypt_width, decrypt_width;  /* chosen values per thread */
-  uint32_t trial_cts, reserved;
+  uint32_t trial_cts, mul_width;          /* mul_width 0: product not timed (no keys) */
   double encrypt_ms[3], decrypt_ms[3];    /* best of 3 runs: [0] 8, [1] 16, [2] 32 values per thread */
+  double mul_ms[3];                       /* the same for the product (INFINITY if not timed) */
 } ckks_tune_report;
 
 int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out);

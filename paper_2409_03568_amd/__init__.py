@@ -68,7 +68,8 @@ class ckks_server_stats_t(C.Structure):
 
 class ckks_tune_report_t(C.Structure):
     _fields_ = [("encrypt_width", C.c_uint32), ("decrypt_width", C.c_uint32), ("trial_cts", C.c_uint32),
-                ("reserved", C.c_uint32), ("encrypt_ms", C.c_double * 3), ("decrypt_ms", C.c_double * 3)]
+                ("mul_width", C.c_uint32), ("encrypt_ms", C.c_double * 3), ("decrypt_ms", C.c_double * 3),
+                ("mul_ms", C.c_double * 3)]
 
 
 class ckks_pipeline_config_t(C.Structure):
@@ -431,12 +432,17 @@ class Context:
         return out
 
     def autotune(self, trial_cts: int = 4096) -> dict:
-        """Time both NTT register blockings for encryption and decryption; keep the faster."""
+        """Time the NTT register blockings for encryption, decryption and (with
+        key-switching keys) the product; keep the fastest of each."""
         r = ckks_tune_report_t()
         _check(lib().ckks_autotune(self.handle, int(trial_cts), C.byref(r)))
-        return {"encrypt_width": r.encrypt_width, "decrypt_width": r.decrypt_width, "trial_cts": r.trial_cts,
-                "encrypt_ms": {8: r.encrypt_ms[0], 16: r.encrypt_ms[1], 32: r.encrypt_ms[2]},
-                "decrypt_ms": {8: r.decrypt_ms[0], 16: r.decrypt_ms[1], 32: r.decrypt_ms[2]}}
+        out = {"encrypt_width": r.encrypt_width, "decrypt_width": r.decrypt_width, "trial_cts": r.trial_cts,
+               "encrypt_ms": {8: r.encrypt_ms[0], 16: r.encrypt_ms[1], 32: r.encrypt_ms[2]},
+               "decrypt_ms": {8: r.decrypt_ms[0], 16: r.decrypt_ms[1], 32: r.decrypt_ms[2]}}
+        if r.mul_width:
+            out["mul_width"] = r.mul_width
+            out["mul_ms"] = {8: r.mul_ms[0], 16: r.mul_ms[1], 32: r.mul_ms[2]}
+        return out
 
 
 class Cache:

@@ -268,6 +268,7 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   // 8-wave workgroups per CU); 8 needs N / 8 <= 1024 threads
   c->logr_enc = N / 8 <= 1024 ? 3 : 4;
   c->logr_dec = 4;
+  c->logr_mul = c->logr_enc;
   hipError_t e = hipSuccess;
   DevTables &d = c->dev;
   if (e == hipSuccess) e = dev_alloc(&d.tw_fwd, (size_t)rows * N);
@@ -329,7 +330,7 @@ int ckks_context_set_ntt_width(ckks_ctx *ctx, uint32_t values_per_thread) {
   if (values_per_thread != 8 && values_per_thread != 16 && values_per_thread != 32)
     return fail(CKKS_EINVAL, "values_per_thread must be 8, 16 or 32");
   if (ctx->N / values_per_thread > 1024) return fail(CKKS_EINVAL, "N / values_per_thread exceeds 1024 threads");
-  ctx->logr_enc = ctx->logr_dec = values_per_thread == 8 ? 3 : (values_per_thread == 16 ? 4 : 5);
+  ctx->logr_enc = ctx->logr_dec = ctx->logr_mul = values_per_thread == 8 ? 3 : (values_per_thread == 16 ? 4 : 5);
   return CKKS_OK;
 }
 

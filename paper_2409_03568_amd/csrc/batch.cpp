@@ -239,18 +239,24 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
   uint8_t *px = nullptr;
   uint64_t *cts = nullptr;
   double *dec = nullptr;
+  uint64_t *prod = nullptr, *scratch = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void **>(&px), trial_cts);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&cts), (uint64_t)trial_cts * ckks_ct_bytes(ctx, L));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&dec), (uint64_t)trial_cts * sizeof(double));
+  if (e == hipSuccess && ctx->has_relin)
+    e = hipMalloc(reinterpret_cast<void **>(&prod), (uint64_t)trial_cts * ckks_ct_bytes(ctx, L));
+  if (e == hipSuccess && ctx->has_relin)
+    e = hipMalloc(reinterpret_cast<void **>(&scratch), mul_scratch_words(trial_cts, (int)L, ctx->N) * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMemset(px, 0x5a, trial_cts);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  const int keep_enc = ctx->logr_enc, keep_dec = ctx->logr_dec;
+  const int keep_enc = ctx->logr_enc, keep_dec = ctx->logr_dec, keep_mul = ctx->logr_mul;
   double enc_ms[3] = {INFINITY, INFINITY, INFINITY}, dec_ms[3] = {INFINITY, INFINITY, INFINITY};
+  double mul_ms[3] = {INFINITY, INFINITY, INFINITY};
   for (int w = 0; w < 3 && e == hipSuccess; w++) {
     if ((ctx->N >> (3 + w)) > 1024) continue;  // more threads than a workgroup holds
-    ctx->logr_enc = ctx->logr_dec = 3 + w;
+    ctx->logr_enc = ctx->logr_dec = ctx->logr_mul = 3 + w;
     EncJob job;
     job.px = px;
     job.n = trial_cts;
@@ -271,6 +277,13 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e == hipSuccess && rep) dec_ms[w] = fmin(dec_ms[w], ms);
+      if (!prod) continue;
+      if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+      if (e == hipSuccess) e = launch_mul(ctx, cts, cts, prod, trial_cts, (int)L, scratch, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && rep) mul_ms[w] = fmin(mul_ms[w], ms);
     }
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -278,25 +291,31 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
   if (px) (void)hipFree(px);
   if (cts) (void)hipFree(cts);
   if (dec) (void)hipFree(dec);
+  if (prod) (void)hipFree(prod);
+  if (scratch) (void)hipFree(scratch);
   if (e != hipSuccess) {
     ctx->logr_enc = keep_enc;
     ctx->logr_dec = keep_dec;
+    ctx->logr_mul = keep_mul;
     return api_fail(CKKS_EDEVICE, "autotune: %s", hipGetErrorString(e));
   }
-  int be = 0, bd = 0;
+  int be = 0, bd = 0, bm = 0;
   for (int w = 1; w < 3; w++) {
     if (enc_ms[w] < enc_ms[be]) be = w;
     if (dec_ms[w] < dec_ms[bd]) bd = w;
+    if (mul_ms[w] < mul_ms[bm]) bm = w;
   }
   ctx->logr_enc = 3 + be;
   ctx->logr_dec = 3 + bd;
+  ctx->logr_mul = prod ? 3 + bm : keep_mul;
   out->encrypt_width = 1u << ctx->logr_enc;
   out->decrypt_width = 1u << ctx->logr_dec;
   out->trial_cts = trial_cts;
-  out->reserved = 0;
+  out->mul_width = prod ? 1u << ctx->logr_mul : 0;
   for (int w = 0; w < 3; w++) {
     out->encrypt_ms[w] = enc_ms[w];
     out->decrypt_ms[w] = dec_ms[w];
+    out->mul_ms[w] = mul_ms[w];
   }
   return CKKS_OK;
 }

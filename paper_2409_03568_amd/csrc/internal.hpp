@@ -91,6 +91,7 @@ struct ckks_ctx {
   double scale = 0;
   int logr_enc = 4;  // 2^logr values per thread in the encryption / key kernels (4 or 5)
   int logr_dec = 4;  // the same for decryption
+  int logr_mul = 4;  // the same for the ciphertext product and its keys
   int rc = 1;    // reduction class of the primes: 0 if all q < 2^40, else 1 (q < 2^50)
   ckks::LimbConsts lc{};
   ckks::LimbConsts *d_lc = nullptr;  // device copy of lc (kernels read it with scalar loads)
@@ -143,10 +144,10 @@ hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, in
 hipError_t launch_relin_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
 hipError_t launch_relin_prepare(const ckks_ctx *c, hipStream_t stream);
 // Relinearized products out = a * b of n ciphertext pairs at `level`; the kernel runs
-// min(n, kMulGroups) workgroups and scratch holds (level + 2) * N words for each.
+// min(n, kMulGroups) workgroups and scratch holds (2 level + 2) * N words for each.
 constexpr uint64_t kMulGroups = 2048;
 inline uint64_t mul_scratch_words(uint64_t n, int level, int N) {
-  return (n < kMulGroups ? n : kMulGroups) * (uint64_t)(level + 2) * (uint64_t)N;
+  return (n < kMulGroups ? n : kMulGroups) * (uint64_t)(2 * level + 2) * (uint64_t)N;
 }
 hipError_t launch_mul(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n, int level,
                       uint64_t *scratch, hipStream_t stream);

@@ -351,18 +351,22 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 
 // ---------------------------------------------------------------------------
 // relinearized product of ciphertext pairs (Sec. 2.2.3), one workgroup per pair:
-//  1. per limb j: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 through the NTT; d0, d1
-//     go to the output, d2 (coefficient domain) to scratch;
-//  2. key switching of d2, prime by prime (the special prime first): for every digit
-//     i (= d2 limb i as an integer below q_i), lift to the prime, transform, and
-//     accumulate its products with key i; back to coefficients;
-//  3. ModDown: out_k = d_k + (acc_k - [acc_k]_qP) qP^-1 mod q_j, [.]_qP centered.
-// All arithmetic exact FP64 on signed representatives kept inside the transform bounds.
+//  1. per limb j, through the NTT: d0 = a0 b0, d1 = a0 b1 + a1 b0 and d2 = a1 b1; d0 and
+//     d1 stay in the NTT domain (parked in the output limb), d2 goes back to
+//     coefficients (the key-switching digit) and its NTT is kept for prime j;
+//  2. key switching, prime by prime with the special prime first: every digit i (d2
+//     limb i as an integer below q_i) is lifted to the prime, transformed (or taken
+//     from step 1 in its own prime) and multiplied by key i;
+//  3. ModDown folded into the last transform: out_j = INTT(d_hat + acc_hat * qP^-1)
+//     - [acc]_qP * qP^-1, [.]_qP the centered coefficient of the special-prime part.
+// Outputs may alias inputs exactly: limb j of a and b is read before limb j of out is
+// written, and nothing else of out is touched in between.  All arithmetic is exact
+// FP64 on signed representatives kept inside the transform bounds.
 // ---------------------------------------------------------------------------
 template <int LOGN, int LOGR, int RC>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
-    k_mul(const uint64_t *__restrict__ A, const uint64_t *__restrict__ Bc, uint64_t *__restrict__ out, uint64_t n,
-          int level, uint64_t *__restrict__ scratch, const LimbConsts *__restrict__ lcp, DevTables dt) {
+    k_mul(const uint64_t *A, const uint64_t *Bc, uint64_t *out, uint64_t n, int level,
+          uint64_t *__restrict__ scratch, const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
   using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
@@ -370,10 +374,12 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   extern __shared__ double lds[];
   const int L = lc.L;
   const uint64_t S_ct = (uint64_t)2 * level * N;
-  // scratch of this workgroup: d2 [level][N] words, then the centered special-prime
-  // accumulators [2][N] doubles; every element is written and read by the same thread
-  uint64_t *d2s = scratch + (uint64_t)blockIdx.x * (uint64_t)(level + 2) * N;
-  double *accP = reinterpret_cast<double *>(d2s + (size_t)level * N);
+  // scratch of this workgroup, every element written and read by one thread:
+  // [level][N] d2 digits, [level][N] NTT(d2) in its own prime, [2][N] centered
+  // special-prime accumulators
+  uint64_t *d2s = scratch + (uint64_t)blockIdx.x * (uint64_t)(2 * level + 2) * N;
+  uint64_t *own = d2s + (size_t)level * N;
+  double *accP = reinterpret_cast<double *>(d2s + (size_t)2 * level * N);
   for (uint64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const uint64_t *a = A + it * S_ct, *b = Bc + it * S_ct;
     uint64_t *o = out + it * S_ct;
@@ -396,24 +402,21 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       ntt_forward<LOGN, LOGR, Red::fwd_big>(y1, lds, tid, tw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        // the a side carries N^-1; every product has operands below q
+        // the a side carries N^-1, except in NTT(d2) for the key products (whose keys do)
+        const int c = tid + T * r;
+        const double a1r = reduce(x1[r], q, qinv);
         const double a0 = reduce(mulmod(x0[r], ninv, q, qinv), q, qinv);
-        const double a1 = reduce(mulmod(x1[r], ninv, q, qinv), q, qinv);
+        const double a1 = reduce(mulmod(a1r, ninv, q, qinv), q, qinv);
         const double b0 = reduce(y0[r], q, qinv), b1 = reduce(y1[r], q, qinv);
-        x0[r] = mulmod(a0, b0, q, qinv);
-        x1[r] = reduce(mulmod(a0, b1, q, qinv) + mulmod(a1, b0, q, qinv), q, qinv);
+        o[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(a0, b0, q, qinv));
+        o[((size_t)level + j) * N + c] = __builtin_bit_cast(
+            uint64_t, reduce(mulmod(a0, b1, q, qinv) + mulmod(a1, b0, q, qinv), q, qinv));
+        own[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(a1r, b1, q, qinv));
         y0[r] = mulmod(a1, b1, q, qinv);
       }
-      ntt_inverse<LOGN, LOGR, Red::inv>(x0, lds, tid, itw, q, qinv);
-      ntt_inverse<LOGN, LOGR, Red::inv>(x1, lds, tid, itw, q, qinv);
       ntt_inverse<LOGN, LOGR, Red::inv>(y0, lds, tid, itw, q, qinv);
 #pragma unroll
-      for (int r = 0; r < R; r++) {
-        const int c = tid + T * r;
-        o[(size_t)j * N + c] = f64_to_u64(canon(x0[r], q, qinv));
-        o[((size_t)level + j) * N + c] = f64_to_u64(canon(x1[r], q, qinv));
-        d2s[(size_t)j * N + c] = f64_to_u64(canon(y0[r], q, qinv));
-      }
+      for (int r = 0; r < R; r++) d2s[(size_t)j * N + tid + T * r] = f64_to_u64(canon(y0[r], q, qinv));
     }
     // 2 + 3. key switching, the special prime (index L) first
     for (int jj = 0; jj <= level; jj++) {
@@ -426,9 +429,14 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       for (int r = 0; r < R; r++) c0[r] = c1[r] = 0.0;
       for (int i = 0; i < level; i++) {
         double x[R];
+        if (i == j) {
 #pragma unroll
-        for (int r = 0; r < R; r++) x[r] = reduce(u64_to_f64(d2s[(size_t)i * N + tid + T * r]), q, qinv);
-        ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, tw, q, qinv);
+          for (int r = 0; r < R; r++) x[r] = __builtin_bit_cast(double, own[(size_t)i * N + tid + T * r]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; r++) x[r] = reduce(u64_to_f64(d2s[(size_t)i * N + tid + T * r]), q, qinv);
+          ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, tw, q, qinv);
+        }
         const double *kb = dt.evk_hat + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -437,9 +445,9 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
           c1[r] = reduce(c1[r] + mulmod(x[r], ka[e], q, qinv), q, qinv);
         }
       }
-      ntt_inverse<LOGN, LOGR, Red::inv>(c0, lds, tid, itw, q, qinv);
-      ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
       if (jj == 0) {
+        ntt_inverse<LOGN, LOGR, Red::inv>(c0, lds, tid, itw, q, qinv);
+        ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
 #pragma unroll
         for (int r = 0; r < R; r++) {
           accP[tid + T * r] = center(c0[r], q, qinv);
@@ -448,14 +456,20 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
         continue;
       }
       const double pinv = lc.pinv[j];
-      const uint64_t qi = lc.qi[j];
+      uint64_t *o0 = o + (size_t)j * N, *o1 = o + ((size_t)level + j) * N;
 #pragma unroll
       for (int r = 0; r < R; r++) {
         const int c = tid + T * r;
-        const double m0 = canon(mulmod(canon(c0[r], q, qinv) - accP[c], pinv, q, qinv), q, qinv);
-        const double m1 = canon(mulmod(canon(c1[r], q, qinv) - accP[N + c], pinv, q, qinv), q, qinv);
-        o[(size_t)j * N + c] = add_mod(o[(size_t)j * N + c], f64_to_u64(m0), qi);
-        o[((size_t)level + j) * N + c] = add_mod(o[((size_t)level + j) * N + c], f64_to_u64(m1), qi);
+        c0[r] = reduce(mulmod(c0[r], pinv, q, qinv) + __builtin_bit_cast(double, o0[c]), q, qinv);
+        c1[r] = reduce(mulmod(c1[r], pinv, q, qinv) + __builtin_bit_cast(double, o1[c]), q, qinv);
+      }
+      ntt_inverse<LOGN, LOGR, Red::inv>(c0, lds, tid, itw, q, qinv);
+      ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int c = tid + T * r;
+        o0[c] = f64_to_u64(canon(c0[r] - mulmod(accP[c], pinv, q, qinv), q, qinv));
+        o1[c] = f64_to_u64(canon(c1[r] - mulmod(accP[N + c], pinv, q, qinv), q, qinv));
       }
     }
   }
@@ -607,9 +621,6 @@ struct Launch {
 
 // All launchers of one ring degree, selecting the thread shape (c->logr) and the
 // reduction class (c->rc) at run time.
-// Register blocking of the multiplication kernels (16 values per thread at every N).
-constexpr int kMulLogR = 4;
-
 template <int LOGN>
 struct RingLaunch {
   template <typename F>
@@ -638,15 +649,15 @@ struct RingLaunch {
     return RingLaunch<LOGN>::pick(c, c->logr_enc, [&](auto L) { return decltype(L)::prepare(c, st); });             \
   }                                                                                                                 \
   hipError_t launch_relin_keygen_##LOGN(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {              \
-    return RingLaunch<LOGN>::pick(c, kMulLogR, [&](auto L) { return decltype(L)::relin_keygen(c, s0, s1, st); });   \
+    return RingLaunch<LOGN>::pick(c, c->logr_mul, [&](auto L) { return decltype(L)::relin_keygen(c, s0, s1, st); });   \
   }                                                                                                                 \
   hipError_t launch_relin_prepare_##LOGN(const ckks_ctx *c, hipStream_t st) {                                       \
-    return RingLaunch<LOGN>::pick(c, kMulLogR, [&](auto L) { return decltype(L)::relin_prepare(c, st); });          \
+    return RingLaunch<LOGN>::pick(c, c->logr_mul, [&](auto L) { return decltype(L)::relin_prepare(c, st); });          \
   }                                                                                                                 \
   hipError_t launch_mul_##LOGN(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,  \
                                int level, uint64_t *scratch, hipStream_t st) {                                      \
     return RingLaunch<LOGN>::pick(                                                                                  \
-        c, kMulLogR, [&](auto L) { return decltype(L)::mul(c, a, b, out, n, level, scratch, st); });                \
+        c, c->logr_mul, [&](auto L) { return decltype(L)::mul(c, a, b, out, n, level, scratch, st); });                \
   }                                                                                                                 \
   hipError_t launch_decrypt_##LOGN(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale,     \
                                    double *out, hipStream_t st) {                                                   \

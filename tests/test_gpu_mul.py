@@ -229,3 +229,19 @@ def test_watermark_single_ciphertext(c1, W):
     want = px.astype(np.float64)
     want[k] += 100.0
     assert np.max(np.abs(dec - want)) < 1e-4
+
+
+def test_autotune_times_the_product(c1, W):
+    ctx, o = c1
+    px = W.config_image(1).reshape(-1)[:16]
+    cts = ctx.encrypt_pixels(_dev(px), (9, 9))
+    before = _np(ctx.mul(cts[0:8], cts[8:16]))
+    _say("[gpu] autotune with key-switching keys")
+    rep = ctx.autotune(256)
+    assert rep["mul_width"] in (8, 16, 32)
+    assert all(np.isfinite(v) and v > 0 for v in rep["mul_ms"].values())
+    after = _np(ctx.mul(cts[0:8], cts[8:16]))
+    assert np.array_equal(before, after)
+    for w in (8, 16, 32):
+        ctx.set_ntt_width(w)
+        assert np.array_equal(_np(ctx.mul(cts[0:8], cts[8:16])), before), w
