@@ -251,231 +251,6 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 }
 
 // ---------------------------------------------------------------------------
-// key-switching keys of s^2 for ciphertext multiplication (Sec. 2.2.3), one workgroup
-// per (digit i, prime j); prime j = L is the special prime qP.  Key i in prime j:
-//   b = -a * s + e_i + [j == i] (qP mod q_i) s^2,  a uniform mod p_j
-// with e_i the Gaussian stream (seed, 0, 48 + i) and a the uniform stream
-// (seed, 0, 64 + 32 i + j), both as in the key generation above.
-// ---------------------------------------------------------------------------
-constexpr uint32_t kTagRkE0 = 48, kTagRkA0 = 64;
-
-template <int LOGN, int LOGR, int RC>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR))
-    k_relin_keygen(uint64_t k0, uint64_t k1, const LimbConsts *__restrict__ lcp, DevTables dt) {
-  using S = Shape<LOGN, LOGR>;
-  using Red = Schedule<LOGN, RC>;
-  constexpr int N = S::N, R = S::R, T = S::T;
-  const LimbConsts &lc = *lcp;
-  extern __shared__ double lds[];
-  uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
-  uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
-  __syncthreads();
-  const int L = lc.L, B = lc.B, i = blockIdx.x, j = blockIdx.y;
-  const double q = lc.q[j], qinv = lc.qinv[j];
-  const uint64_t qi = lc.qi[j];
-  const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
-  uint32_t smp[R];
-  const uint32_t etag = kTagRkE0 + (uint32_t)i;
-  draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, tid, k0, k1, 0, etag, etag, etag);
-  const uint64_t limit = 0ULL - ((~0ULL % qi + 1) % qi);
-  uint64_t *kb = dt.evk + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
-  double a[R];
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    const uint32_t c = (uint32_t)(tid + T * r);
-    uint64_t val = 0;
-    bool done = false;
-    for (uint64_t att = 0; !done; att++) {
-      const Philox4 w = philox4x64_10(0, kTagRkA0 + 32u * (uint32_t)i + (uint32_t)j, att * N + c, 0, k0, k1);
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        if (!done && w.w[k] < limit) {
-          val = w.w[k] % qi;
-          done = true;
-        }
-      }
-    }
-    ka[c] = val;
-    a[r] = (double)val;
-  }
-  // s_hat and s_hat * N^-1 in this prime
-  double sh[R], shn[R];
-#pragma unroll
-  for (int r = 0; r < R; r++) sh[r] = (double)dt.s[tid + T * r];
-  ntt_forward<LOGN, LOGR, Red::fwd_small>(sh, lds, tid, tw, q, qinv);
-  const double ninv = lc.ninv[j];
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    sh[r] = reduce(sh[r], q, qinv);
-    shn[r] = reduce(mulmod(sh[r], ninv, q, qinv), q, qinv);
-  }
-  ntt_forward<LOGN, LOGR, Red::fwd_big>(a, lds, tid, tw, q, qinv);
-  const bool own = (j == i);
-  const double pm = own ? lc.pmod[i] : 0.0;
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    double v = -mulmod(a[r], shn[r], q, qinv);
-    if (own) v += mulmod(mulmod(sh[r], shn[r], q, qinv), pm, q, qinv);
-    a[r] = reduce(v, q, qinv);
-  }
-  ntt_inverse<LOGN, LOGR, Red::inv>(a, lds, tid, itw, q, qinv);
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    const double e = (double)smp_g(smp[r], 8, B);
-    kb[tid + T * r] = (uint64_t)canon(a[r] + e, q, qinv);
-  }
-}
-
-// NTT-domain copies of the key-switching keys times N^-1 (grid: digits x primes x 2).
-template <int LOGN, int LOGR, int RC>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR))
-    k_relin_prepare(const LimbConsts *__restrict__ lcp, DevTables dt) {
-  using S = Shape<LOGN, LOGR>;
-  using Red = Schedule<LOGN, RC>;
-  constexpr int N = S::N, R = S::R, T = S::T;
-  const LimbConsts &lc = *lcp;
-  extern __shared__ double lds[];
-  const int tid = threadIdx.x, i = blockIdx.x, j = blockIdx.y, k = blockIdx.z, L = lc.L;
-  const double q = lc.q[j], qinv = lc.qinv[j];
-  const size_t off = ((((size_t)i * (L + 1) + j) * 2) + k) * N;
-  double x[R];
-#pragma unroll
-  for (int r = 0; r < R; r++) x[r] = u64_to_f64(dt.evk[off + tid + T * r]);
-  ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd + (size_t)j * N, q, qinv);
-#pragma unroll
-  for (int r = 0; r < R; r++)
-    dt.evk_hat[off + elem_index<LOGN, LOGR, S::LAST>(tid, r)] = reduce(mulmod(x[r], lc.ninv[j], q, qinv), q, qinv);
-}
-
-// ---------------------------------------------------------------------------
-// relinearized product of ciphertext pairs (Sec. 2.2.3), one workgroup per pair:
-//  1. per limb j, through the NTT: d0 = a0 b0, d1 = a0 b1 + a1 b0 and d2 = a1 b1; d0 and
-//     d1 stay in the NTT domain (parked in the output limb), d2 goes back to
-//     coefficients (the key-switching digit) and its NTT is kept for prime j;
-//  2. key switching, prime by prime with the special prime first: every digit i (d2
-//     limb i as an integer below q_i) is lifted to the prime, transformed (or taken
-//     from step 1 in its own prime) and multiplied by key i;
-//  3. ModDown folded into the last transform: out_j = INTT(d_hat + acc_hat * qP^-1)
-//     - [acc]_qP * qP^-1, [.]_qP the centered coefficient of the special-prime part.
-// Outputs may alias inputs exactly: limb j of a and b is read before limb j of out is
-// written, and nothing else of out is touched in between.  All arithmetic is exact
-// FP64 on signed representatives kept inside the transform bounds.
-// ---------------------------------------------------------------------------
-template <int LOGN, int LOGR, int RC>
-__global__ void __launch_bounds__(1 << (LOGN - LOGR))
-    k_mul(const uint64_t *A, const uint64_t *Bc, uint64_t *out, uint64_t n, int level,
-          uint64_t *__restrict__ scratch, const LimbConsts *__restrict__ lcp, DevTables dt) {
-  using S = Shape<LOGN, LOGR>;
-  using Red = Schedule<LOGN, RC>;
-  constexpr int N = S::N, R = S::R, T = S::T;
-  const LimbConsts &lc = *lcp;
-  extern __shared__ double lds[];
-  const int L = lc.L;
-  const uint64_t S_ct = (uint64_t)2 * level * N;
-  // scratch of this workgroup, every element written and read by one thread:
-  // [level][N] d2 digits, [level][N] NTT(d2) in its own prime, [2][N] centered
-  // special-prime accumulators
-  uint64_t *d2s = scratch + (uint64_t)blockIdx.x * (uint64_t)(2 * level + 2) * N;
-  uint64_t *own = d2s + (size_t)level * N;
-  double *accP = reinterpret_cast<double *>(d2s + (size_t)2 * level * N);
-  for (uint64_t it = blockIdx.x; it < n; it += gridDim.x) {
-    const uint64_t *a = A + it * S_ct, *b = Bc + it * S_ct;
-    uint64_t *o = out + it * S_ct;
-    // 1. tensor product, limb by limb
-    for (int j = 0; j < level; j++) {
-      const int tid = opaque(threadIdx.x);
-      const double q = lc.q[j], qinv = lc.qinv[j], ninv = lc.ninv[j];
-      const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
-      double x0[R], x1[R], y0[R], y1[R];
-#pragma unroll
-      for (int r = 0; r < R; r++) {
-        x0[r] = u64_to_f64(a[(size_t)j * N + tid + T * r]);
-        x1[r] = u64_to_f64(a[((size_t)level + j) * N + tid + T * r]);
-        y0[r] = u64_to_f64(b[(size_t)j * N + tid + T * r]);
-        y1[r] = u64_to_f64(b[((size_t)level + j) * N + tid + T * r]);
-      }
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(x0, lds, tid, tw, q, qinv);
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(x1, lds, tid, tw, q, qinv);
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(y0, lds, tid, tw, q, qinv);
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(y1, lds, tid, tw, q, qinv);
-#pragma unroll
-      for (int r = 0; r < R; r++) {
-        // the a side carries N^-1, except in NTT(d2) for the key products (whose keys do)
-        const int c = tid + T * r;
-        const double a1r = reduce(x1[r], q, qinv);
-        const double a0 = reduce(mulmod(x0[r], ninv, q, qinv), q, qinv);
-        const double a1 = reduce(mulmod(a1r, ninv, q, qinv), q, qinv);
-        const double b0 = reduce(y0[r], q, qinv), b1 = reduce(y1[r], q, qinv);
-        o[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(a0, b0, q, qinv));
-        o[((size_t)level + j) * N + c] = __builtin_bit_cast(
-            uint64_t, reduce(mulmod(a0, b1, q, qinv) + mulmod(a1, b0, q, qinv), q, qinv));
-        own[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(a1r, b1, q, qinv));
-        y0[r] = mulmod(a1, b1, q, qinv);
-      }
-      ntt_inverse<LOGN, LOGR, Red::inv>(y0, lds, tid, itw, q, qinv);
-#pragma unroll
-      for (int r = 0; r < R; r++) d2s[(size_t)j * N + tid + T * r] = f64_to_u64(canon(y0[r], q, qinv));
-    }
-    // 2 + 3. key switching, the special prime (index L) first
-    for (int jj = 0; jj <= level; jj++) {
-      const int tid = opaque(threadIdx.x);
-      const int j = jj == 0 ? L : jj - 1;
-      const double q = lc.q[j], qinv = lc.qinv[j];
-      const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
-      double c0[R], c1[R];
-#pragma unroll
-      for (int r = 0; r < R; r++) c0[r] = c1[r] = 0.0;
-      for (int i = 0; i < level; i++) {
-        double x[R];
-        if (i == j) {
-#pragma unroll
-          for (int r = 0; r < R; r++) x[r] = __builtin_bit_cast(double, own[(size_t)i * N + tid + T * r]);
-        } else {
-#pragma unroll
-          for (int r = 0; r < R; r++) x[r] = reduce(u64_to_f64(d2s[(size_t)i * N + tid + T * r]), q, qinv);
-          ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, tw, q, qinv);
-        }
-        const double *kb = dt.evk_hat + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-          const unsigned e = elem_index<LOGN, LOGR, S::LAST>(tid, r);
-          c0[r] = reduce(c0[r] + mulmod(x[r], kb[e], q, qinv), q, qinv);
-          c1[r] = reduce(c1[r] + mulmod(x[r], ka[e], q, qinv), q, qinv);
-        }
-      }
-      if (jj == 0) {
-        ntt_inverse<LOGN, LOGR, Red::inv>(c0, lds, tid, itw, q, qinv);
-        ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-          accP[tid + T * r] = center(c0[r], q, qinv);
-          accP[N + tid + T * r] = center(c1[r], q, qinv);
-        }
-        continue;
-      }
-      const double pinv = lc.pinv[j];
-      uint64_t *o0 = o + (size_t)j * N, *o1 = o + ((size_t)level + j) * N;
-#pragma unroll
-      for (int r = 0; r < R; r++) {
-        const int c = tid + T * r;
-        c0[r] = reduce(mulmod(c0[r], pinv, q, qinv) + __builtin_bit_cast(double, o0[c]), q, qinv);
-        c1[r] = reduce(mulmod(c1[r], pinv, q, qinv) + __builtin_bit_cast(double, o1[c]), q, qinv);
-      }
-      ntt_inverse<LOGN, LOGR, Red::inv>(c0, lds, tid, itw, q, qinv);
-      ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
-#pragma unroll
-      for (int r = 0; r < R; r++) {
-        const int c = tid + T * r;
-        o0[c] = f64_to_u64(canon(c0[r] - mulmod(accP[c], pinv, q, qinv), q, qinv));
-        o1[c] = f64_to_u64(canon(c1[r] - mulmod(accP[N + c], pinv, q, qinv), q, qinv));
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // decryption of limb 0 and decoding of slot 0:
 //   d = c0 + INTT(NTT(c1) * s_hat); out = sum_j center(d_j) cos(pi j/N) / scale
 // ---------------------------------------------------------------------------
@@ -548,6 +323,12 @@ static hipError_t set_lds() {
   if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
   return e;
 }
+
+}  // namespace ckks
+
+#include "k_mul_impl.hpp"
+
+namespace ckks {
 
 template <int LOGN, int LOGR, int RC>
 struct Launch {

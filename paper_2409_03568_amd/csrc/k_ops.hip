@@ -131,10 +131,11 @@ struct FilterConsts {
   double h;             // floor(q_last / 2)
 };
 
-constexpr int kFilterWaves = kRowThreads / 64;
+constexpr int kFilterWaves = 8;
+constexpr int kFilterThreads = 64 * kFilterWaves;
 
 template <int KW, int LV, int XT>
-__global__ void __launch_bounds__(kRowThreads)
+__global__ void __launch_bounds__(kFilterThreads)
     k_mean_filter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t H, uint32_t W, uint32_t y_begin,
                   uint32_t y_end, int log_n, uint32_t groups, FilterConsts fc) {
   constexpr int RAD = KW / 2, XC = XT + 2 * RAD;
@@ -148,8 +149,9 @@ __global__ void __launch_bounds__(kRowThreads)
   const uint32_t rest = lb / groups;
   const int poly = (int)(rest & 1);
   const int j = (int)((rest >> 1) * 64 + (threadIdx.x & 63));
+  // a wave past the right edge reads clamped columns and writes nothing, but keeps to
+  // the workgroup's per-row barrier
   const uint64_t x0 = ((uint64_t)g * kFilterWaves + (threadIdx.x >> 6)) * XT;
-  if (x0 >= W) return;
   uint32_t xs[XC];
 #pragma unroll
   for (int d = 0; d < XC; d++) {
@@ -225,6 +227,9 @@ __global__ void __launch_bounds__(kRowThreads)
             ring[s][t][i] = nh[t][i];
           }
       }
+      // keep the waves of the workgroup on one row: the halo columns two neighbouring
+      // waves share are then read at about the same time and served by the cache
+      __syncthreads();
     }
   }
 }
@@ -307,7 +312,7 @@ static hipError_t filter_t(const uint64_t *in, uint64_t *out, uint32_t H, uint32
   const uint64_t groups = (tiles + kFilterWaves - 1) / kFilterWaves;
   const uint64_t blocks = groups * 2 * (((uint64_t)1 << log_n) / 64);
   if (blocks > 0xffffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_mean_filter<KW, LV, XT>), dim3((uint32_t)blocks), dim3(kRowThreads), 0, st, in, out, H, W,
+  hipLaunchKernelGGL((k_mean_filter<KW, LV, XT>), dim3((uint32_t)blocks), dim3(kFilterThreads), 0, st, in, out, H, W,
                      y0, y1, log_n, (uint32_t)groups, fc);
   return hipGetLastError();
 }
