@@ -161,11 +161,47 @@ CKKS_HD void stage_fence() {
 #endif
 }
 
-// Forward (Cooley-Tukey) stages of one pass; reduce every value after stage s if bit s of RED.
+// Twiddles of one pass.  Stage l of the pass (global stage s = start + l) uses the 2^l
+// factors tw[2^s + (blk << l) + t], t < 2^l, of each of the thread's G groups; slot
+// (2^l - 1 + t) of a group holds factor t.  Where a pass needs few of them they are
+// loaded into registers before the pass's LDS exchange, so their latency hides behind
+// the barriers instead of stalling every stage.
+template <int LOGN, int LOGR, int PASS>
+struct PassTw {
+  using S = NttShape<LOGN, LOGR>;
+  static constexpr int P = S::len(PASS), G = S::R >> P, PER = (1 << P) - 1, COUNT = G * PER;
+  static constexpr bool kPrefetch = COUNT <= 8;
+  static constexpr int SLOTS = kPrefetch ? COUNT : 1;
+  double w[SLOTS];  // the prefetched factors (unused without prefetch)
+};
+
+template <int LOGN, int LOGR, int PASS>
+CKKS_HD void tw_prefetch(PassTw<LOGN, LOGR, PASS> &regs, int tid_in, const double *__restrict__ tw) {
+  using S = NttShape<LOGN, LOGR>;
+  using PT = PassTw<LOGN, LOGR, PASS>;
+  double *w = regs.w;
+  if constexpr (PT::kPrefetch) {
+    const int tid = opaque(tid_in);
+    constexpr int S0 = S::start(PASS), P = PT::P, LTLO = LOGN - S0 - P;
+#pragma unroll
+    for (int u = 0; u < PT::G; u++) {
+      const unsigned blk = ((unsigned)tid + (unsigned)S::T * u) >> LTLO;
+#pragma unroll
+      for (int l = 0; l < P; l++)
+#pragma unroll
+        for (int t = 0; t < (1 << l); t++) w[u * PT::PER + (1 << l) - 1 + t] = tw[(1u << (S0 + l)) + (blk << l) + t];
+    }
+  }
+}
+
+// Forward (Cooley-Tukey) stages of one pass; reduce every value after stage s if bit s of
+// RED.  Twiddles come from w when the pass prefetches them, else from tw.
 template <int LOGN, int LOGR, int PASS, uint32_t RED>
-CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ tw, double q, double qinv) {
+CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ tw,
+                      const PassTw<LOGN, LOGR, PASS> &regs, double q, double qinv) {
   const int tid = opaque(tid_in);
   using S = NttShape<LOGN, LOGR>;
+  using PT = PassTw<LOGN, LOGR, PASS>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;
 #pragma unroll
@@ -179,7 +215,12 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 #pragma unroll
       for (int k = 0; k < (1 << P); k++) {
         if (k & half) continue;
-        const double W = tw[(1u << s) + (blk << l) + (unsigned)(k >> (P - l))];
+        const unsigned t = (unsigned)(k >> (P - l));
+        double W;
+        if constexpr (PT::kPrefetch)
+          W = regs.w[u * PT::PER + (1 << l) - 1 + t];
+        else
+          W = tw[(1u << s) + (blk << l) + t];
         ct_butterfly(x[u * (1 << P) + k], x[u * (1 << P) + k + half], W, q, qinv);
       }
       if ((RED >> s) & 1u) {
@@ -194,9 +235,11 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 // Inverse (Gentleman-Sande) stages of one pass, in decreasing stage order; reduce the sum
 // outputs after stage s if bit s of RED.
 template <int LOGN, int LOGR, int PASS, uint32_t RED>
-CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ itw, double q, double qinv) {
+CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restrict__ itw,
+                      const PassTw<LOGN, LOGR, PASS> &regs, double q, double qinv) {
   const int tid = opaque(tid_in);
   using S = NttShape<LOGN, LOGR>;
+  using PT = PassTw<LOGN, LOGR, PASS>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
   constexpr int LTLO = LOGN - S0 - P;
 #pragma unroll
@@ -210,7 +253,12 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 #pragma unroll
       for (int k = 0; k < (1 << P); k++) {
         if (k & half) continue;
-        const double W = itw[(1u << s) + (blk << l) + (unsigned)(k >> (P - l))];
+        const unsigned t = (unsigned)(k >> (P - l));
+        double W;
+        if constexpr (PT::kPrefetch)
+          W = regs.w[u * PT::PER + (1 << l) - 1 + t];
+        else
+          W = itw[(1u << s) + (blk << l) + t];
         double &X = x[u * (1 << P) + k];
         double &Y = x[u * (1 << P) + k + half];
         gs_butterfly(X, Y, W, q, qinv);
@@ -249,11 +297,13 @@ template <int LOGN, int LOGR, uint32_t RED, int PASS = 1>
 __device__ __forceinline__ void fwd_rest(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ tw,
                                          double q, double qinv) {
   if constexpr (PASS < NttShape<LOGN, LOGR>::NPASS) {
+    PassTw<LOGN, LOGR, PASS> w;
+    tw_prefetch<LOGN, LOGR, PASS>(w, tid, tw);
     __syncthreads();
     lds_store<LOGN, LOGR, PASS - 1>(lds, x, tid);
     __syncthreads();
     lds_load<LOGN, LOGR, PASS>(lds, x, tid);
-    fwd_pass<LOGN, LOGR, PASS, RED>(x, tid, tw, q, qinv);
+    fwd_pass<LOGN, LOGR, PASS, RED>(x, tid, tw, w, q, qinv);
     fwd_rest<LOGN, LOGR, RED, PASS + 1>(x, lds, tid, tw, q, qinv);
   }
 }
@@ -262,7 +312,9 @@ __device__ __forceinline__ void fwd_rest(double (&x)[1 << LOGR], double *lds, in
 template <int LOGN, int LOGR, uint32_t RED>
 __device__ __forceinline__ void ntt_forward(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ tw,
                                             double q, double qinv) {
-  fwd_pass<LOGN, LOGR, 0, RED>(x, tid, tw, q, qinv);
+  PassTw<LOGN, LOGR, 0> w;
+  tw_prefetch<LOGN, LOGR, 0>(w, tid, tw);
+  fwd_pass<LOGN, LOGR, 0, RED>(x, tid, tw, w, q, qinv);
   fwd_rest<LOGN, LOGR, RED, 1>(x, lds, tid, tw, q, qinv);
 }
 
@@ -270,11 +322,13 @@ template <int LOGN, int LOGR, uint32_t RED, int PASS>
 __device__ __forceinline__ void inv_rest(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
                                          double q, double qinv) {
   if constexpr (PASS >= 0) {
+    PassTw<LOGN, LOGR, PASS> w;
+    tw_prefetch<LOGN, LOGR, PASS>(w, tid, itw);
     __syncthreads();
     lds_store<LOGN, LOGR, PASS + 1>(lds, x, tid);
     __syncthreads();
     lds_load<LOGN, LOGR, PASS>(lds, x, tid);
-    inv_pass<LOGN, LOGR, PASS, RED>(x, tid, itw, q, qinv);
+    inv_pass<LOGN, LOGR, PASS, RED>(x, tid, itw, w, q, qinv);
     inv_rest<LOGN, LOGR, RED, PASS - 1>(x, lds, tid, itw, q, qinv);
   }
 }
@@ -285,7 +339,9 @@ template <int LOGN, int LOGR, uint32_t RED>
 __device__ __forceinline__ void ntt_inverse(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
                                             double q, double qinv) {
   constexpr int LAST = NttShape<LOGN, LOGR>::NPASS - 1;
-  inv_pass<LOGN, LOGR, LAST, RED>(x, tid, itw, q, qinv);
+  PassTw<LOGN, LOGR, LAST> w;
+  tw_prefetch<LOGN, LOGR, LAST>(w, tid, itw);
+  inv_pass<LOGN, LOGR, LAST, RED>(x, tid, itw, w, q, qinv);
   inv_rest<LOGN, LOGR, RED, LAST - 1>(x, lds, tid, itw, q, qinv);
 }
 

@@ -34,7 +34,9 @@ void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double
   double x[S::R];
   for (int t = 0; t < S::T; t++) {
     for (int r = 0; r < S::R; r++) x[r] = X[t][r];
-    fwd_pass<LOGN, LOGR, 0, RED>(x, t, tw, q, qinv);
+    PassTw<LOGN, LOGR, 0> w;
+    tw_prefetch<LOGN, LOGR, 0>(w, t, tw);
+    fwd_pass<LOGN, LOGR, 0, RED>(x, t, tw, w, q, qinv);
     for (int r = 0; r < S::R; r++) X[t][r] = x[r];
   }
   track(X);
@@ -57,7 +59,9 @@ void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double
       for (int h : hit) g_lds_bijective = g_lds_bijective && h <= 1;
       for (int t = 0; t < S::T; t++) {
         lds_load<LOGN, LOGR, P>(lds.data(), x, t);
-        fwd_pass<LOGN, LOGR, P, RED>(x, t, tw, q, qinv);
+        PassTw<LOGN, LOGR, P> w;
+        tw_prefetch<LOGN, LOGR, P>(w, t, tw);
+        fwd_pass<LOGN, LOGR, P, RED>(x, t, tw, w, q, qinv);
         for (int r = 0; r < S::R; r++) X[t][r] = x[r];
       }
       track(X);
@@ -77,7 +81,9 @@ void inv(std::vector<std::vector<double>> &X, const double *itw, double q, doubl
   double x[S::R];
   for (int t = 0; t < S::T; t++) {
     for (int r = 0; r < S::R; r++) x[r] = X[t][r];
-    inv_pass<LOGN, LOGR, LAST, RED>(x, t, itw, q, qinv);
+    PassTw<LOGN, LOGR, LAST> w;
+    tw_prefetch<LOGN, LOGR, LAST>(w, t, itw);
+    inv_pass<LOGN, LOGR, LAST, RED>(x, t, itw, w, q, qinv);
     for (int r = 0; r < S::R; r++) X[t][r] = x[r];
   }
   track(X);
@@ -90,7 +96,9 @@ void inv(std::vector<std::vector<double>> &X, const double *itw, double q, doubl
       }
       for (int t = 0; t < S::T; t++) {
         lds_load<LOGN, LOGR, P>(lds.data(), x, t);
-        inv_pass<LOGN, LOGR, P, RED>(x, t, itw, q, qinv);
+        PassTw<LOGN, LOGR, P> w;
+        tw_prefetch<LOGN, LOGR, P>(w, t, itw);
+        inv_pass<LOGN, LOGR, P, RED>(x, t, itw, w, q, qinv);
         for (int r = 0; r < S::R; r++) X[t][r] = x[r];
       }
       track(X);
