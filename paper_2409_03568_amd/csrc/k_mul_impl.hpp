@@ -106,17 +106,19 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 
 // ---------------------------------------------------------------------------
 // relinearized product of ciphertext pairs (Sec. 2.2.3), one workgroup per pair:
-//  1. per limb j, through the NTT: d0 = a0 b0, d1 = a0 b1 + a1 b0 and d2 = a1 b1; d0 and
-//     d1 stay in the NTT domain (parked in the output limb), d2 goes back to
-//     coefficients (the key-switching digit) and its NTT is kept for prime j;
+//  1. per limb j, through the NTT: d0 = a0 b0, d1 = a0 b1 + a1 b0 and d2 = a1 b1 (at most
+//     three transforms held at once); d0 and d1 stay in the NTT domain (parked in the
+//     output limb), d2 goes back to coefficients (the key-switching digit) and its NTT
+//     is kept for prime j;
 //  2. key switching, prime by prime with the special prime first: every digit i (d2
 //     limb i as an integer below q_i) is lifted to the prime, transformed (or taken
 //     from step 1 in its own prime) and multiplied by key i;
 //  3. ModDown folded into the last transform: out_j = INTT(d_hat + acc_hat * qP^-1)
 //     - [acc]_qP * qP^-1, [.]_qP the centered coefficient of the special-prime part.
-// Outputs may alias inputs exactly: limb j of a and b is read before limb j of out is
-// written, and nothing else of out is touched in between.  All arithmetic is exact
-// FP64 on signed representatives kept inside the transform bounds.
+// Outputs may alias inputs exactly: each residue row (poly, limb) of out is first written
+// after the same rows of a and b have been read, and after step 1 only out and scratch
+// are read.  All arithmetic is exact FP64 on signed representatives kept inside the
+// transform bounds.
 // ---------------------------------------------------------------------------
 template <int LOGN, int LOGR, int RC>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
@@ -143,35 +145,48 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       const int tid = opaque(threadIdx.x);
       const double q = lc.q[j], qinv = lc.qinv[j], ninv = lc.ninv[j];
       const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
-      double x0[R], x1[R], y0[R], y1[R];
+      // three transforms live at a time: a1 b0 waits in this limb's own-prime scratch row
+      // until b1 arrives (not in out, which may be b)
+      uint64_t *o0 = o + (size_t)j * N, *o1 = o + ((size_t)level + j) * N;
+      double x[R], y[R], z[R];
+#pragma unroll
+      for (int r = 0; r < R; r++) x[r] = u64_to_f64(a[(size_t)j * N + tid + T * r]);
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, tw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        x0[r] = u64_to_f64(a[(size_t)j * N + tid + T * r]);
-        x1[r] = u64_to_f64(a[((size_t)level + j) * N + tid + T * r]);
-        y0[r] = u64_to_f64(b[(size_t)j * N + tid + T * r]);
-        y1[r] = u64_to_f64(b[((size_t)level + j) * N + tid + T * r]);
+        x[r] = reduce(mulmod(x[r], ninv, q, qinv), q, qinv);  // a0 (the a side carries N^-1)
+        y[r] = u64_to_f64(b[(size_t)j * N + tid + T * r]);
       }
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(x0, lds, tid, tw, q, qinv);
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(x1, lds, tid, tw, q, qinv);
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(y0, lds, tid, tw, q, qinv);
-      ntt_forward<LOGN, LOGR, Red::fwd_big>(y1, lds, tid, tw, q, qinv);
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(y, lds, tid, tw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        // the a side carries N^-1, except in NTT(d2) for the key products (whose keys do)
+        y[r] = reduce(y[r], q, qinv);  // b0
+        o0[tid + T * r] = __builtin_bit_cast(uint64_t, mulmod(x[r], y[r], q, qinv));  // d0
+        z[r] = u64_to_f64(a[((size_t)level + j) * N + tid + T * r]);
+      }
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(z, lds, tid, tw, q, qinv);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        z[r] = reduce(z[r], q, qinv);  // a1 without N^-1
+        const double a1 = reduce(mulmod(z[r], ninv, q, qinv), q, qinv);
+        own[(size_t)j * N + tid + T * r] = __builtin_bit_cast(uint64_t, mulmod(a1, y[r], q, qinv));  // a1 b0
+        y[r] = u64_to_f64(b[((size_t)level + j) * N + tid + T * r]);
+      }
+      ntt_forward<LOGN, LOGR, Red::fwd_big>(y, lds, tid, tw, q, qinv);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
         const int c = tid + T * r;
-        const double a1r = reduce(x1[r], q, qinv);
-        const double a0 = reduce(mulmod(x0[r], ninv, q, qinv), q, qinv);
-        const double a1 = reduce(mulmod(a1r, ninv, q, qinv), q, qinv);
-        const double b0 = reduce(y0[r], q, qinv), b1 = reduce(y1[r], q, qinv);
-        o[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(a0, b0, q, qinv));
-        o[((size_t)level + j) * N + c] = __builtin_bit_cast(
-            uint64_t, reduce(mulmod(a0, b1, q, qinv) + mulmod(a1, b0, q, qinv), q, qinv));
-        own[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(a1r, b1, q, qinv));
-        y0[r] = mulmod(a1, b1, q, qinv);
+        const double b1 = reduce(y[r], q, qinv);
+        o1[c] = __builtin_bit_cast(
+            uint64_t, reduce(mulmod(x[r], b1, q, qinv) + __builtin_bit_cast(double, own[(size_t)j * N + c]), q,
+                             qinv));  // d1
+        // NTT(d2) for the key product in prime j (keys carry N^-1), and d2 itself
+        own[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(z[r], b1, q, qinv));
+        y[r] = mulmod(reduce(mulmod(z[r], ninv, q, qinv), q, qinv), b1, q, qinv);
       }
-      ntt_inverse<LOGN, LOGR, Red::inv>(y0, lds, tid, itw, q, qinv);
+      ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, itw, q, qinv);
 #pragma unroll
-      for (int r = 0; r < R; r++) d2s[(size_t)j * N + tid + T * r] = f64_to_u64(canon(y0[r], q, qinv));
+      for (int r = 0; r < R; r++) d2s[(size_t)j * N + tid + T * r] = f64_to_u64(canon(y[r], q, qinv));
     }
     // 2 + 3. key switching, the special prime (index L) first
     for (int jj = 0; jj <= level; jj++) {

@@ -133,18 +133,23 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
         double y[R];
 #pragma unroll
         for (int r = 0; r < R; r++) y[r] = mulmod(x[r], pkh[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
-        ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv);
+        // the plaintext (poly 0) and the Gaussian term, loaded before the final exchange
+        double add[R];
+        ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, [&] {
+#pragma unroll
+          for (int r = 0; r < R; r++) {
+            const int j = tid + T * r;
+            add[r] = (double)smp_g(sample(r), poly == 0 ? 8 : 16, B);
+            if (poly == 0) {
+              add[r] += __builtin_rint(value * dt.enc_T[j]);
+              if (BRIGHT) add[r] += __builtin_rint(fb * dt.cosj[j]);
+            }
+          }
+        });
         uint64_t *dst = out + ((size_t)poly * L + l) * N;
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-          const int j = tid + T * r;
-          double v = y[r] + (double)smp_g(sample(r), poly == 0 ? 8 : 16, B);
-          if (poly == 0) {
-            v += __builtin_rint(value * dt.enc_T[j]);
-            if (BRIGHT) v += __builtin_rint(fb * dt.cosj[j]);
-          }
-          __builtin_nontemporal_store((uint64_t)canon(v, q, qinv), dst + j);
-        }
+        for (int r = 0; r < R; r++)
+          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), dst + tid + T * r);
       }
     }
   }
@@ -286,13 +291,17 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd, q, qinv);
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = mulmod(x[r], dt.s_hat[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
-    ntt_inverse<LOGN, LOGR, Red::inv>(x, lds, tid, dt.tw_inv, q, qinv);
+    // c0 is loaded from HBM before the final exchange of the transform
+    uint64_t c0w[R];
+    ntt_inverse<LOGN, LOGR, Red::inv>(x, lds, tid, dt.tw_inv, q, qinv, [&] {
+#pragma unroll
+      for (int r = 0; r < R; r++) c0w[r] = __builtin_nontemporal_load(c0 + tid + T * r);
+    });
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-      const int j = tid + T * r;
-      const double d = center(x[r] + u64_to_f64(__builtin_nontemporal_load(c0 + j)), q, qinv);
-      acc = __builtin_fma(d, dt.cosj[j], acc);
+      const double d = center(x[r] + u64_to_f64(c0w[r]), q, qinv);
+      acc = __builtin_fma(d, dt.cosj[tid + T * r], acc);
     }
     // workgroup sum in a fixed order: wave butterflies, then the waves in sequence
 #pragma unroll

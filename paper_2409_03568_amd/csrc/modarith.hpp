@@ -75,21 +75,18 @@ CKKS_HD void gs_butterfly(double &X, double &Y, double W, double q, double qinv)
 }
 
 // ---------------------------------------------------------------------------
-// conversions between canonical uint64 residues (< 2^53) and exact doubles
+// conversions between canonical uint64 residues (< 2^52) and exact doubles
 // ---------------------------------------------------------------------------
-constexpr double kTwo32 = 4294967296.0;
-constexpr double kTwoM32 = 1.0 / 4294967296.0;
+// For an integer 0 <= x < 2^52 the double 2^52 + x is exact and its bit pattern is that
+// of 2^52 with x in the low 52 (mantissa) bits, so each conversion is one integer and
+// one floating-point operation.
+constexpr double kTwo52 = 4503599627370496.0;
+constexpr uint64_t kTwo52Bits = 0x4330000000000000ull;
 
-CKKS_HD double u64_to_f64(uint64_t x) {
-  return __builtin_fma((double)(uint32_t)(x >> 32), kTwo32, (double)(uint32_t)x);
-}
+CKKS_HD double u64_to_f64(uint64_t x) { return __builtin_bit_cast(double, x | kTwo52Bits) - kTwo52; }
 
-// x integer-valued in [0, 2^53)
-CKKS_HD uint64_t f64_to_u64(double x) {
-  const uint32_t hi = (uint32_t)(x * kTwoM32);  // truncation = floor for x >= 0
-  const uint32_t lo = (uint32_t)__builtin_fma(-(double)hi, kTwo32, x);
-  return ((uint64_t)hi << 32) | lo;
-}
+// x integer-valued in [0, 2^52)
+CKKS_HD uint64_t f64_to_u64(double x) { return __builtin_bit_cast(uint64_t, x + kTwo52) - kTwo52Bits; }
 
 // ---------------------------------------------------------------------------
 // 64-bit integer helpers for canonical uint64 residues (elementwise kernels)

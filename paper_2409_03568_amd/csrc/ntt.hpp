@@ -318,31 +318,42 @@ __device__ __forceinline__ void ntt_forward(double (&x)[1 << LOGR], double *lds,
   fwd_rest<LOGN, LOGR, RED, 1>(x, lds, tid, tw, q, qinv);
 }
 
-template <int LOGN, int LOGR, uint32_t RED, int PASS>
+// Passes PASS..0 of the inverse transform; before_last() runs just before the exchange
+// that precedes the final pass (a place for the caller's own loads, whose latency then
+// hides behind that exchange).
+template <int LOGN, int LOGR, uint32_t RED, int PASS, class F>
 __device__ __forceinline__ void inv_rest(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
-                                         double q, double qinv) {
+                                         double q, double qinv, F &&before_last) {
   if constexpr (PASS >= 0) {
     PassTw<LOGN, LOGR, PASS> w;
     tw_prefetch<LOGN, LOGR, PASS>(w, tid, itw);
+    if constexpr (PASS == 0) before_last();
     __syncthreads();
     lds_store<LOGN, LOGR, PASS + 1>(lds, x, tid);
     __syncthreads();
     lds_load<LOGN, LOGR, PASS>(lds, x, tid);
     inv_pass<LOGN, LOGR, PASS, RED>(x, tid, itw, w, q, qinv);
-    inv_rest<LOGN, LOGR, RED, PASS - 1>(x, lds, tid, itw, q, qinv);
+    inv_rest<LOGN, LOGR, RED, PASS - 1>(x, lds, tid, itw, q, qinv, before_last);
   }
 }
 
 // Whole inverse transform (without the factor 1/N) from the last-pass layout to the
-// first-pass layout.
-template <int LOGN, int LOGR, uint32_t RED>
+// first-pass layout.  before_last() runs before the final exchange (see inv_rest).
+template <int LOGN, int LOGR, uint32_t RED, class F>
 __device__ __forceinline__ void ntt_inverse(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
-                                            double q, double qinv) {
+                                            double q, double qinv, F &&before_last) {
   constexpr int LAST = NttShape<LOGN, LOGR>::NPASS - 1;
+  static_assert(LAST >= 1, "the transform has at least two passes");
   PassTw<LOGN, LOGR, LAST> w;
   tw_prefetch<LOGN, LOGR, LAST>(w, tid, itw);
   inv_pass<LOGN, LOGR, LAST, RED>(x, tid, itw, w, q, qinv);
-  inv_rest<LOGN, LOGR, RED, LAST - 1>(x, lds, tid, itw, q, qinv);
+  inv_rest<LOGN, LOGR, RED, LAST - 1>(x, lds, tid, itw, q, qinv, before_last);
+}
+
+template <int LOGN, int LOGR, uint32_t RED>
+__device__ __forceinline__ void ntt_inverse(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
+                                            double q, double qinv) {
+  ntt_inverse<LOGN, LOGR, RED>(x, lds, tid, itw, q, qinv, [] {});
 }
 
 }  // namespace ckks
