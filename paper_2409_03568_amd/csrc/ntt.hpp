@@ -27,14 +27,30 @@
 
 namespace ckks {
 
+// Pass structure of a transform over N = 2^LOGN values, R = 2^LOGR per thread: the
+// stages are split into NPASS passes, the first of FIRST (1..LOGR) stages and the others
+// of LOGR.  Putting the short pass first keeps the last passes' thread layouts equal on
+// the wave-index bits, so their exchanges stay inside a wave (see same_wave_sets).
 template <int LOGN, int LOGR>
 struct NttShape {
   static constexpr int N = 1 << LOGN;
   static constexpr int R = 1 << LOGR;
   static constexpr int T = N / R;
   static constexpr int NPASS = (LOGN + LOGR - 1) / LOGR;
-  static constexpr int start(int p) { return p * LOGR; }
-  static constexpr int len(int p) { return p == NPASS - 1 ? LOGN - p * LOGR : LOGR; }
+  static constexpr int FIRST = LOGN - (NPASS - 1) * LOGR;
+  static constexpr int start(int p) { return p == 0 ? 0 : FIRST + (p - 1) * LOGR; }
+  static constexpr int len(int p) { return p == 0 ? FIRST : LOGR; }
+  // element-index bit that bit b of the thread index occupies in pass p (see elem_index)
+  static constexpr int tid_bit_pos(int p, int b) {
+    return b < LOGN - start(p) - len(p) ? b : b + len(p);
+  }
+  // true when every wave holds the same set of elements in passes a and b: the wave-index
+  // bits of the thread index (bits 6 and up) sit at the same element bits in both
+  static constexpr bool same_wave_sets(int a, int b) {
+    for (int t = 6; (1 << t) < T; t++)
+      if (tid_bit_pos(a, t) != tid_bit_pos(b, t)) return false;
+    return true;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -110,7 +126,10 @@ struct Schedule {
 // ---------------------------------------------------------------------------
 // layouts
 // ---------------------------------------------------------------------------
-// Element index held in register r by thread tid during pass PASS.
+// Element index held in register r by thread tid during pass PASS.  A pass of P stages
+// splits r into the butterfly index k (P bits) and, when P < LOGR, a group index u:
+// r = k * G + u with G = R / 2^P, so that in the first pass register r of thread tid
+// holds element tid + T * r (the coefficient order the kernels load and store).
 // (Indices are unsigned 32-bit so that loads can address a uniform base plus a 32-bit
 // per-lane offset instead of building a 64-bit address per load.)
 template <int LOGN, int LOGR, int PASS>
@@ -118,7 +137,7 @@ CKKS_HD unsigned elem_index(unsigned tid, unsigned r) {
   using S = NttShape<LOGN, LOGR>;
   constexpr int S0 = S::start(PASS), P = S::len(PASS);
   constexpr int LTLO = LOGN - S0 - P;  // log2 of the smallest butterfly distance in the pass
-  const unsigned u = r >> P, k = r & ((1u << P) - 1);
+  const unsigned u = r & ((1u << (LOGR - P)) - 1), k = r >> (LOGR - P);
   const unsigned g = tid + (unsigned)S::T * u;
   const unsigned blk = g >> LTLO, off = g & ((1u << LTLO) - 1);
   return (blk << (LOGN - S0)) + (k << LTLO) + off;
@@ -221,11 +240,11 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
           W = regs.w[u * PT::PER + (1 << l) - 1 + t];
         else
           W = tw[(1u << s) + (blk << l) + t];
-        ct_butterfly(x[u * (1 << P) + k], x[u * (1 << P) + k + half], W, q, qinv);
+        ct_butterfly(x[k * G + u], x[(k + half) * G + u], W, q, qinv);
       }
       if ((RED >> s) & 1u) {
 #pragma unroll
-        for (int k = 0; k < (1 << P); k++) x[u * (1 << P) + k] = reduce(x[u * (1 << P) + k], q, qinv);
+        for (int k = 0; k < (1 << P); k++) x[k * G + u] = reduce(x[k * G + u], q, qinv);
       }
       stage_fence();
     }
@@ -259,8 +278,8 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
           W = regs.w[u * PT::PER + (1 << l) - 1 + t];
         else
           W = itw[(1u << s) + (blk << l) + t];
-        double &X = x[u * (1 << P) + k];
-        double &Y = x[u * (1 << P) + k + half];
+        double &X = x[k * G + u];
+        double &Y = x[(k + half) * G + u];
         gs_butterfly(X, Y, W, q, qinv);
         if ((RED >> s) & 1u) X = reduce(X, q, qinv);
       }
@@ -290,6 +309,34 @@ CKKS_HD void lds_load(const double *lds, double (&x)[1 << LOGR], int tid_in) {
   for (int r = 0; r < (1 << LOGR); r++) x[r] = base[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(0, r))];
 }
 
+// Synchronisation of the LDS exchange between two passes.  Where each wave writes exactly
+// the LDS slots it reads back (same_wave_sets), only the wave's own accesses must stay in
+// order, and LDS operations of one wave are performed in issue order: a wave-scope fence
+// keeps the compiler from reordering them and no workgroup barrier is needed.  The first
+// exchange of a transform keeps its leading barrier, since the slots' previous users are
+// not known there.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE_LOCAL, bool FIRST_EXCHANGE>
+__device__ __forceinline__ void exchange_lead() {
+  if constexpr (WAVE_LOCAL && !FIRST_EXCHANGE)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void exchange_mid() {
+  if constexpr (WAVE_LOCAL)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
 // Passes 1..NPASS-1 of the forward transform (pass 0 is run by the caller on the
 // first-pass layout); ends with x in the last-pass layout.  Contains barriers: every
 // thread of the workgroup must call it.
@@ -297,11 +344,12 @@ template <int LOGN, int LOGR, uint32_t RED, int PASS = 1>
 __device__ __forceinline__ void fwd_rest(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ tw,
                                          double q, double qinv) {
   if constexpr (PASS < NttShape<LOGN, LOGR>::NPASS) {
+    constexpr bool kLocal = NttShape<LOGN, LOGR>::same_wave_sets(PASS - 1, PASS);
     PassTw<LOGN, LOGR, PASS> w;
     tw_prefetch<LOGN, LOGR, PASS>(w, tid, tw);
-    __syncthreads();
+    exchange_lead<kLocal, PASS == 1>();
     lds_store<LOGN, LOGR, PASS - 1>(lds, x, tid);
-    __syncthreads();
+    exchange_mid<kLocal>();
     lds_load<LOGN, LOGR, PASS>(lds, x, tid);
     fwd_pass<LOGN, LOGR, PASS, RED>(x, tid, tw, w, q, qinv);
     fwd_rest<LOGN, LOGR, RED, PASS + 1>(x, lds, tid, tw, q, qinv);
@@ -325,12 +373,14 @@ template <int LOGN, int LOGR, uint32_t RED, int PASS, class F>
 __device__ __forceinline__ void inv_rest(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
                                          double q, double qinv, F &&before_last) {
   if constexpr (PASS >= 0) {
+    using NS = NttShape<LOGN, LOGR>;
+    constexpr bool kLocal = NS::same_wave_sets(PASS + 1, PASS);
     PassTw<LOGN, LOGR, PASS> w;
     tw_prefetch<LOGN, LOGR, PASS>(w, tid, itw);
     if constexpr (PASS == 0) before_last();
-    __syncthreads();
+    exchange_lead<kLocal, PASS == NS::NPASS - 2>();
     lds_store<LOGN, LOGR, PASS + 1>(lds, x, tid);
-    __syncthreads();
+    exchange_mid<kLocal>();
     lds_load<LOGN, LOGR, PASS>(lds, x, tid);
     inv_pass<LOGN, LOGR, PASS, RED>(x, tid, itw, w, q, qinv);
     inv_rest<LOGN, LOGR, RED, PASS - 1>(x, lds, tid, itw, q, qinv, before_last);

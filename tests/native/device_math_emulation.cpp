@@ -8,6 +8,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <vector>
 
@@ -21,6 +22,29 @@ namespace {
 
 double g_max_abs = 0;
 bool g_lds_bijective = true;
+bool g_wave_local_ok = true;
+int g_wave_local_count = 0;
+
+// An exchange from the layout of pass A to that of pass B that the kernels run without a
+// workgroup barrier must have every wave write exactly the LDS slots it then reads.
+template <int LOGN, int LOGR, int A, int B>
+void check_wave_local() {
+  using S = NttShape<LOGN, LOGR>;
+  if constexpr (S::same_wave_sets(A, B)) {
+    g_wave_local_count++;
+    for (int w = 0; w * 64 < S::T; w++) {
+      std::vector<unsigned> wr, rd;
+      for (int t = w * 64; t < w * 64 + 64 && t < S::T; t++)
+        for (int r = 0; r < S::R; r++) {
+          wr.push_back(lds_pos<LOGR>(elem_index<LOGN, LOGR, A>(t, r)));
+          rd.push_back(lds_pos<LOGR>(elem_index<LOGN, LOGR, B>(t, r)));
+        }
+      std::sort(wr.begin(), wr.end());
+      std::sort(rd.begin(), rd.end());
+      if (wr != rd) g_wave_local_ok = false;
+    }
+  }
+}
 
 void track(const std::vector<std::vector<double>> &X) {
   for (auto &v : X)
@@ -43,6 +67,7 @@ void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double
   auto step = [&](auto pass_c) {
     constexpr int P = decltype(pass_c)::value;
     if constexpr (P >= 1 && P < S::NPASS) {
+      check_wave_local<LOGN, LOGR, P - 1, P>();
       std::vector<int> hit(LdsSlots<LOGN, LOGR>::value, 0);
       for (int t = 0; t < S::T; t++) {
         for (int r = 0; r < S::R; r++) {
@@ -90,6 +115,7 @@ void inv(std::vector<std::vector<double>> &X, const double *itw, double q, doubl
   auto step = [&](auto pass_c) {
     constexpr int P = decltype(pass_c)::value;
     if constexpr (P >= 0 && P < LAST) {
+      check_wave_local<LOGN, LOGR, P + 1, P>();
       for (int t = 0; t < S::T; t++) {
         for (int r = 0; r < S::R; r++) x[r] = X[t][r];
         lds_store<LOGN, LOGR, P + 1>(lds.data(), x, t);
@@ -171,9 +197,13 @@ int emu_negacyclic(const int64_t *a, const uint64_t *b, uint64_t *c, int log_n, 
 
 double emu_max_abs(void) { return g_max_abs; }
 int emu_lds_bijective(void) { return g_lds_bijective ? 1 : 0; }
+int emu_wave_local_ok(void) { return g_wave_local_ok ? 1 : 0; }
+int emu_wave_local_count(void) { return g_wave_local_count; }
 void emu_reset_max(void) {
   g_max_abs = 0;
   g_lds_bijective = true;
+  g_wave_local_ok = true;
+  g_wave_local_count = 0;
 }
 
 double emu_mulmod(double a, double w, double q) { return mulmod(a, w, q, 1.0 / q); }

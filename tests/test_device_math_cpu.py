@@ -40,6 +40,8 @@ def emu():
     L.emu_negacyclic.restype = C.c_int
     L.emu_max_abs.restype = C.c_double
     L.emu_lds_bijective.restype = C.c_int
+    L.emu_wave_local_ok.restype = C.c_int
+    L.emu_wave_local_count.restype = C.c_int
     for f in ("emu_mulmod",):
         getattr(L, f).argtypes = [C.c_double, C.c_double, C.c_double]
         getattr(L, f).restype = C.c_double
@@ -95,6 +97,10 @@ def test_emulated_ntt_product_matches_oracle(emu, oracle_mod, log_n, bits, logr)
             assert np.array_equal(c, ref), (name, q)
             assert emu.emu_max_abs() < 2.0**52, name
             assert emu.emu_lds_bijective() == 1
+            # exchanges run without a workgroup barrier keep every wave on its own LDS slots
+            assert emu.emu_wave_local_ok() == 1
+            if (log_n, logr) == (13, 3):
+                assert emu.emu_wave_local_count() == 6  # 2 of the 4 exchanges in each of 3 transforms
 
 
 def test_reduction_schedules(emu):
