@@ -127,12 +127,24 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 #pragma unroll
       for (int r = 0; r < R; r++) x[r] = (double)smp_t(sample(r));
       ntt_forward<LOGN, LOGR, Red::fwd_small>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
+      // both pointwise products at once (one wait for the key loads; x is then dead and
+      // the second product takes its registers through the first inverse transform)
+      double y[R], y1[R];
+      {
+        const double *pk0 = dt.pk_hat + (size_t)l * N, *pk1 = dt.pk_hat + ((size_t)L + l) * N;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const unsigned e = elem_index<LOGN, LOGR, S::LAST>(tid, r);
+          y[r] = mulmod(x[r], pk0[e], q, qinv);
+          y1[r] = mulmod(x[r], pk1[e], q, qinv);
+        }
+      }
 #pragma unroll 1
       for (int poly = 0; poly < 2; poly++) {
-        const double *pkh = dt.pk_hat + ((size_t)poly * L + l) * N;
-        double y[R];
+        if (poly == 1) {
 #pragma unroll
-        for (int r = 0; r < R; r++) y[r] = mulmod(x[r], pkh[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
+          for (int r = 0; r < R; r++) y[r] = y1[r];
+        }
         // the plaintext (poly 0) and the Gaussian term, loaded before the final exchange
         double add[R];
         ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, [&] {

@@ -139,7 +139,8 @@ CKKS_HD unsigned elem_index(unsigned tid, unsigned r) {
   constexpr int LTLO = LOGN - S0 - P;  // log2 of the smallest butterfly distance in the pass
   const unsigned u = r & ((1u << (LOGR - P)) - 1), k = r >> (LOGR - P);
   const unsigned g = tid + (unsigned)S::T * u;
-  const unsigned blk = g >> LTLO, off = g & ((1u << LTLO) - 1);
+  // in the first pass every g is below 2^LTLO, so blk = 0 (stated, for the compiler)
+  const unsigned blk = PASS == 0 ? 0u : g >> LTLO, off = PASS == 0 ? g : g & ((1u << LTLO) - 1);
   return (blk << (LOGN - S0)) + (k << LTLO) + off;
 }
 
@@ -204,7 +205,8 @@ CKKS_HD void tw_prefetch(PassTw<LOGN, LOGR, PASS> &regs, int tid_in, const doubl
     constexpr int S0 = S::start(PASS), P = PT::P, LTLO = LOGN - S0 - P;
 #pragma unroll
     for (int u = 0; u < PT::G; u++) {
-      const unsigned blk = ((unsigned)tid + (unsigned)S::T * u) >> LTLO;
+      // first pass: blk = 0, so its factors are the same for every thread (scalar loads)
+      const unsigned blk = PASS == 0 ? 0u : ((unsigned)tid + (unsigned)S::T * u) >> LTLO;
 #pragma unroll
       for (int l = 0; l < P; l++)
 #pragma unroll
@@ -226,7 +228,7 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 #pragma unroll
   for (int u = 0; u < G; u++) {
     const unsigned g = (unsigned)tid + (unsigned)S::T * u;
-    const unsigned blk = g >> LTLO;
+    const unsigned blk = PASS == 0 ? 0u : g >> LTLO;
 #pragma unroll
     for (int l = 0; l < P; l++) {
       const int s = S0 + l;
@@ -264,7 +266,7 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 #pragma unroll
   for (int u = 0; u < G; u++) {
     const unsigned g = (unsigned)tid + (unsigned)S::T * u;
-    const unsigned blk = g >> LTLO;
+    const unsigned blk = PASS == 0 ? 0u : g >> LTLO;
 #pragma unroll
     for (int l = P - 1; l >= 0; l--) {
       const int s = S0 + l;
