@@ -144,19 +144,25 @@ CKKS_HD unsigned elem_index(unsigned tid, unsigned r) {
   return (blk << (LOGN - S0)) + (k << LTLO) + off;
 }
 
-// LDS position of element e: one padding slot after every 2^(LOGR-1) elements.  In each
-// pass the 16 lanes of a quarter-wave then fall on 16 different 8-byte banks (lanes one
-// apart, in pairs 2^(LOGN-S0) apart, or 2^(P) apart in the last pass, which the padding
-// turns into an odd stride); for 16 values per thread every pass is conflict-free, for 32
-// the middle pass keeps a two-way conflict.  The padding depends almost only on bits the
-// register index does not change, so one thread's accesses mostly share a base address
-// with immediate offsets.
+// LDS position of element e: an XOR swizzle of the low four index bits with the four bits
+// above bit LOGR, e ^ ((e >> LOGR) & 15) -- a permutation, so the exchange needs N slots
+// and no padding.  The LDS serves one quarter-wave (16 lanes) of 8-byte accesses per
+// cycle from 16 8-byte banks (slot mod 16).  In every pass the 16 lanes of a quarter
+// differ in four element bits: bits 0..3 (passes whose smallest butterfly distance is at
+// least 16), or bits 0..L-1 together with L+P..3+P (distance 2^L < 16, P stages), or bits
+// P..P+3 (distance 1); in each case the swizzle maps those bits one to one onto the four
+// bank bits, so no access of an exchange has a bank conflict.
 template <int LOGR>
-CKKS_HD unsigned lds_pos(unsigned e) { return e + (e >> (LOGR - 1)); }
+CKKS_HD unsigned lds_pos(unsigned e) { return e ^ ((e >> LOGR) & 15u); }
 template <int LOGN, int LOGR>
 struct LdsSlots {
-  static constexpr int value = (1 << LOGN) + ((1 << LOGN) >> (LOGR - 1));
+  static constexpr int value = 1 << LOGN;
 };
+// Slot of element t | r (thread part t, register part r on disjoint bits) from tb =
+// lds_pos(t) and pr = lds_pos(r): the swizzle is linear over XOR, so the slot is tb ^ pr;
+// the bits of pr above bit 3 are those of r, disjoint from tb's, so they can be added as
+// a compile-time offset and only pr's low four bits need an XOR with the base.
+CKKS_HD unsigned lds_slot(unsigned tb, unsigned pr) { return (tb ^ (pr & 15u)) + (pr & ~15u); }
 
 // ---------------------------------------------------------------------------
 // passes
@@ -292,23 +298,33 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
 
 // The element index is the bitwise OR of a thread part, elem_index(tid, 0), and a
 // register part, elem_index(0, r), on disjoint bits (the thread index and the register
-// index fill different bit fields of it), and the padded position keeps that split:
-// lds_pos(a | b) = lds_pos(a) + lds_pos(b) for disjoint a, b.  So each thread computes one
-// base address per exchange and the registers use compile-time offsets from it.
+// index fill different bit fields of it), so each thread computes one base slot per
+// exchange and each register adds a compile-time offset, after an XOR of the base with
+// the register part's low swizzled bits where those are not zero (lds_slot).
+// (The slot arithmetic is done on byte offsets, so each distinct low part costs one XOR
+// and the high part is an instruction's immediate offset.)
 template <int LOGN, int LOGR, int PASS>
 CKKS_HD void lds_store(double *lds, const double (&x)[1 << LOGR], int tid_in) {
   const int tid = opaque(tid_in);
-  double *base = lds + lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>((unsigned)tid, 0));
+  const unsigned tb8 = lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>((unsigned)tid, 0)) << 3;
+  char *bytes = reinterpret_cast<char *>(lds);
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) base[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(0, r))] = x[r];
+  for (int r = 0; r < (1 << LOGR); r++) {
+    const unsigned pr = lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(0, r));
+    *reinterpret_cast<double *>(bytes + ((tb8 ^ ((pr & 15u) << 3)) + ((pr & ~15u) << 3))) = x[r];
+  }
 }
 
 template <int LOGN, int LOGR, int PASS>
 CKKS_HD void lds_load(const double *lds, double (&x)[1 << LOGR], int tid_in) {
   const int tid = opaque(tid_in);
-  const double *base = lds + lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>((unsigned)tid, 0));
+  const unsigned tb8 = lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>((unsigned)tid, 0)) << 3;
+  const char *bytes = reinterpret_cast<const char *>(lds);
 #pragma unroll
-  for (int r = 0; r < (1 << LOGR); r++) x[r] = base[lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(0, r))];
+  for (int r = 0; r < (1 << LOGR); r++) {
+    const unsigned pr = lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(0, r));
+    x[r] = *reinterpret_cast<const double *>(bytes + ((tb8 ^ ((pr & 15u) << 3)) + ((pr & ~15u) << 3)));
+  }
 }
 
 // Synchronisation of the LDS exchange between two passes.  Where each wave writes exactly

@@ -22,6 +22,20 @@ namespace {
 
 double g_max_abs = 0;
 bool g_lds_bijective = true;
+bool g_lds_conflict_free = true;
+
+// Every access of an exchange (one register, one quarter-wave of 16 lanes) must fall on 16
+// different 8-byte banks (slot mod 16).
+template <int LOGN, int LOGR, int PASS>
+void check_banks() {
+  using S = NttShape<LOGN, LOGR>;
+  for (int r = 0; r < S::R; r++)
+    for (int q0 = 0; q0 < S::T; q0 += 16) {
+      unsigned seen = 0;
+      for (int t = q0; t < q0 + 16 && t < S::T; t++) seen |= 1u << (lds_pos<LOGR>(elem_index<LOGN, LOGR, PASS>(t, r)) & 15u);
+      if (seen != 0xffffu) g_lds_conflict_free = false;
+    }
+}
 bool g_wave_local_ok = true;
 int g_wave_local_count = 0;
 
@@ -68,6 +82,8 @@ void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double
     constexpr int P = decltype(pass_c)::value;
     if constexpr (P >= 1 && P < S::NPASS) {
       check_wave_local<LOGN, LOGR, P - 1, P>();
+      check_banks<LOGN, LOGR, P - 1>();
+      check_banks<LOGN, LOGR, P>();
       std::vector<int> hit(LdsSlots<LOGN, LOGR>::value, 0);
       for (int t = 0; t < S::T; t++) {
         for (int r = 0; r < S::R; r++) {
@@ -76,7 +92,8 @@ void fwd(std::vector<std::vector<double>> &X, const double *tw, double q, double
           hit[lds_pos<LOGR>(e)]++;
           // the split the kernels use: thread base plus a per-register offset
           const unsigned et = elem_index<LOGN, LOGR, P - 1>(t, 0), er = elem_index<LOGN, LOGR, P - 1>(0, r);
-          if ((et & er) != 0 || (et | er) != e || lds_pos<LOGR>(e) != lds_pos<LOGR>(et) + lds_pos<LOGR>(er))
+          if ((et & er) != 0 || (et | er) != e ||
+              lds_pos<LOGR>(e) != lds_slot(lds_pos<LOGR>(et), lds_pos<LOGR>(er)))
             g_lds_bijective = false;
         }
         lds_store<LOGN, LOGR, P - 1>(lds.data(), x, t);
@@ -197,11 +214,13 @@ int emu_negacyclic(const int64_t *a, const uint64_t *b, uint64_t *c, int log_n, 
 
 double emu_max_abs(void) { return g_max_abs; }
 int emu_lds_bijective(void) { return g_lds_bijective ? 1 : 0; }
+int emu_lds_conflict_free(void) { return g_lds_conflict_free ? 1 : 0; }
 int emu_wave_local_ok(void) { return g_wave_local_ok ? 1 : 0; }
 int emu_wave_local_count(void) { return g_wave_local_count; }
 void emu_reset_max(void) {
   g_max_abs = 0;
   g_lds_bijective = true;
+  g_lds_conflict_free = true;
   g_wave_local_ok = true;
   g_wave_local_count = 0;
 }
