@@ -64,7 +64,7 @@ typedef struct ckks_cache ckks_cache;
  *  log_scale   Delta = 2^log_scale.  Pixel coefficients must stay below q_{L-1}/2:
  *              256 * 2^(log_scale + 1 - log_n) < q_{L-1} is required.
  *  sigma       standard deviation of the discrete Gaussian errors (0 = no noise).
- *  gauss_bound tail cut B of the Gaussian; 0 selects floor(6 sigma).  B <= 64.
+ *  gauss_bound tail cut B of the Gaussian; 0 selects floor(6 sigma).  B <= 63.
  *  primes      NULL selects the L largest primes below 2^prime_bits that are
  *              1 mod 2N, in descending order; otherwise L caller-chosen primes
  *              (each 1 mod 2N, exactly prime_bits bits, distinct), copied.      */

@@ -87,7 +87,7 @@ std::string resolve(uint32_t log_n, uint32_t L, uint32_t bits, uint32_t log_scal
   int B = 0;
   if (sigma > 0.0) {
     B = gauss_bound ? (int)gauss_bound : (int)floor(6.0 * sigma);
-    if (B < 1 || B > kMaxGaussBound) return "gauss_bound must be in [1, 64]";
+    if (B < 1 || B > kMaxGaussBound) return "gauss_bound must be in [1, 63]";
   }
   const uint64_t twoN = 2ULL << log_n;
   std::vector<uint64_t> q;

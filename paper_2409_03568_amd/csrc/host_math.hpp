@@ -9,7 +9,7 @@ namespace ckks {
 namespace host {
 
 constexpr int kMaxLimbs = 16;
-constexpr int kMaxGaussBound = 64;
+constexpr int kMaxGaussBound = 63;  // a sample plus B fits 7 bits of the packed sample word
 
 struct Resolved {
   int log_n = 0;

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
   uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
-  uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
+  uint16_t *lds16 = reinterpret_cast<uint16_t *>(lds);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
   __syncthreads();
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   const double *tw = dt.tw_fwd + (size_t)j * N, *itw = dt.tw_inv + (size_t)j * N;
   uint32_t smp[R];
   const uint32_t etag = kTagRkE0 + (uint32_t)i;
-  draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, tid, k0, k1, 0, etag, etag, etag);
+  draw_samples<LOGN, LOGR>(smp, lds16, cdt, B, tid, k0, k1, 0, etag, etag, etag);
   const uint64_t limit = 0ULL - ((~0ULL % qi + 1) % qi);
   uint64_t *kb = dt.evk + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
   double a[R];
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   ntt_inverse<LOGN, LOGR, Red::inv>(a, lds, tid, itw, q, qinv);
 #pragma unroll
   for (int r = 0; r < R; r++) {
-    const double e = (double)smp_g(smp[r], 8, B);
+    const double e = (double)smp_g(smp[r], kSmpShiftG2, B);
     kb[tid + T * r] = (uint64_t)canon(a[r] + e, q, qinv);
   }
 }

@@ -21,20 +21,28 @@ struct Shape : NttShape<LOGN, LOGR> {
   // table, and a reduction area
   static constexpr int SLOTS = LdsSlots<LOGN, LOGR>::value;
   static constexpr size_t lds_bytes = sizeof(double) * ((size_t)SLOTS + kCdtSlots + 64);
-  // Encryption also keeps the packed samples of the current ciphertext (4 bytes per
-  // coefficient) in LDS after the above when that fits a CU's 160 KiB, instead of in
-  // registers for the whole ciphertext.
-  static constexpr size_t smp_bytes = sizeof(uint32_t) * ((size_t)1 << LOGN);
-  static constexpr bool kSmpLds = lds_bytes + smp_bytes <= 160 * 1024;
-  static constexpr size_t enc_lds_bytes = lds_bytes + (kSmpLds ? smp_bytes : 0);
+  // Encryption also keeps the packed samples of the current ciphertext (2 bytes per
+  // coefficient) in LDS when that fits a CU's 160 KiB, instead of in registers for the
+  // whole ciphertext.
+  static constexpr size_t smp_bytes = sizeof(uint16_t) * ((size_t)1 << LOGN);
+  // When a second exchange space fits as well (N <= 8192), encryption runs the two
+  // inverse transforms of a limb as one paired transform; its second space follows the
+  // reduction area, and the packed samples follow that when they fit too.
+  static constexpr bool kDual = lds_bytes + sizeof(double) * (size_t)SLOTS <= 160 * 1024;
+  static constexpr size_t enc_base_bytes = lds_bytes + (kDual ? sizeof(double) * (size_t)SLOTS : 0);
+  static constexpr bool kSmpLds = enc_base_bytes + smp_bytes <= 160 * 1024;
+  static constexpr size_t enc_lds_bytes = enc_base_bytes + (kSmpLds ? smp_bytes : 0);
 };
 
 // Draw the packed samples of one polynomial triple into LDS: word j of dst holds
-// coefficient j as (t1 + 1) | (g2 + B) << 8 | (g3 + B) << 16, where t1 is the ternary
+// coefficient j as (t1 + 1) | (g2 + B) << 2 | (g3 + B) << 9, where t1 is the ternary
 // value of stream tag1 and g2, g3 the Gaussian values of streams tag2, tag3 (all at
-// Philox index t).  Each thread draws whole Philox blocks; ends with a barrier.
+// Philox index t; 0 <= g + B <= 2B <= 126).  Each thread draws whole Philox blocks; ends
+// with a barrier.
+constexpr int kSmpShiftG2 = 2, kSmpShiftG3 = 9;
+
 template <int LOGN, int LOGR>
-__device__ __forceinline__ void draw_samples(uint32_t *dst, const uint64_t *cdt, int B, int tid, uint64_t k0,
+__device__ __forceinline__ void draw_samples(uint16_t *dst, const uint64_t *cdt, int B, int tid, uint64_t k0,
                                              uint64_t k1, uint64_t t, uint32_t tag1, uint32_t tag2, uint32_t tag3) {
   using S = NttShape<LOGN, LOGR>;
   static_assert(S::R >= 4, "each thread draws whole Philox blocks");
@@ -44,33 +52,33 @@ __device__ __forceinline__ void draw_samples(uint32_t *dst, const uint64_t *cdt,
     const Philox4 pv = philox4x64_10(t, tag1, b, 0, k0, k1);
     const Philox4 pa = philox4x64_10(t, tag2, b, 0, k0, k1);
     const Philox4 pb = philox4x64_10(t, tag3, b, 0, k0, k1);
-    uint4 packed;
-    uint32_t *pw = reinterpret_cast<uint32_t *>(&packed);
+    uint32_t w2[2];
 #pragma unroll
     for (int w = 0; w < 4; w++) {
       const uint32_t tv = (uint32_t)(ternary_of(pv.w[w]) + 1);
       const uint32_t ga = (uint32_t)(gauss_of(pa.w[w], cdt, B) + B);
       const uint32_t gb = (uint32_t)(gauss_of(pb.w[w], cdt, B) + B);
-      pw[w] = tv | (ga << 8) | (gb << 16);
+      const uint32_t word = tv | (ga << kSmpShiftG2) | (gb << kSmpShiftG3);
+      w2[w >> 1] = (w & 1) ? (w2[w >> 1] | (word << 16)) : word;
     }
-    reinterpret_cast<uint4 *>(dst)[b] = packed;
+    reinterpret_cast<uint2 *>(dst)[b] = make_uint2(w2[0], w2[1]);
   }
   __syncthreads();
 }
 
 // The same, read back in the first-pass layout: smp[r] holds coefficient tid + T*r.
 template <int LOGN, int LOGR>
-__device__ __forceinline__ void draw_samples(uint32_t (&smp)[1 << LOGR], uint32_t *lds32, const uint64_t *cdt,
+__device__ __forceinline__ void draw_samples(uint32_t (&smp)[1 << LOGR], uint16_t *lds16, const uint64_t *cdt,
                                              int B, int tid, uint64_t k0, uint64_t k1, uint64_t t, uint32_t tag1,
                                              uint32_t tag2, uint32_t tag3) {
   using S = NttShape<LOGN, LOGR>;
-  draw_samples<LOGN, LOGR>(lds32, cdt, B, tid, k0, k1, t, tag1, tag2, tag3);
+  draw_samples<LOGN, LOGR>(lds16, cdt, B, tid, k0, k1, t, tag1, tag2, tag3);
 #pragma unroll
-  for (int r = 0; r < S::R; r++) smp[r] = lds32[tid + S::T * r];
+  for (int r = 0; r < S::R; r++) smp[r] = lds16[tid + S::T * r];
 }
 
-__device__ __forceinline__ int smp_t(uint32_t s) { return (int)(s & 0xffu) - 1; }
-__device__ __forceinline__ int smp_g(uint32_t s, int shift, int B) { return (int)((s >> shift) & 0xffu) - B; }
+__device__ __forceinline__ int smp_t(uint32_t s) { return (int)(s & 3u) - 1; }
+__device__ __forceinline__ int smp_g(uint32_t s, int shift, int B) { return (int)((s >> shift) & 0x7fu) - B; }
 
 // ---------------------------------------------------------------------------
 // fused plain encryption: per ciphertext, per limb
@@ -94,8 +102,8 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
   uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
-  uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
-  uint32_t *smpl = reinterpret_cast<uint32_t *>(lds + S::SLOTS + kCdtSlots + 64);
+  uint16_t *lds16 = reinterpret_cast<uint16_t *>(lds);
+  uint16_t *smpl = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(lds) + S::enc_base_bytes);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
   const int L = lc.L, B = lc.B;
@@ -113,13 +121,13 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     if constexpr (S::kSmpLds)
       draw_samples<LOGN, LOGR>(smpl, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
     else
-      draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
+      draw_samples<LOGN, LOGR>(smp, lds16, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
     for (int l = 0; l < L; l++) {
       const double q = lc.q[l], qinv = lc.qinv[l];
       const int tid = opaque(threadIdx.x);
       auto sample = [&](int r) -> uint32_t {
         if constexpr (S::kSmpLds)
-          return smpl[tid + T * r];
+          return (uint32_t)smpl[tid + T * r];
         else
           return smp[r];
       };
@@ -139,6 +147,28 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
           y1[r] = mulmod(x[r], pk1[e], q, qinv);
         }
       }
+      if constexpr (S::kDual) {
+        // c0 and c1 of this limb through one paired inverse transform; the plaintext and
+        // e0 are loaded before its final exchange
+        double add[R];
+        ntt_inverse2<LOGN, LOGR, Red::inv>(y, y1, lds, lds + S::SLOTS + kCdtSlots + 64, tid,
+                                           dt.tw_inv + (size_t)l * N, q, qinv, [&] {
+#pragma unroll
+          for (int r = 0; r < R; r++) {
+            const int j = tid + T * r;
+            add[r] = (double)smp_g(sample(r), kSmpShiftG2, B) + __builtin_rint(value * dt.enc_T[j]);
+            if (BRIGHT) add[r] += __builtin_rint(fb * dt.cosj[j]);
+          }
+        });
+        uint64_t *dst0 = out + (size_t)l * N, *dst1 = out + ((size_t)L + l) * N;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), dst0 + tid + T * r);
+          __builtin_nontemporal_store(f64_to_u64(canon(y1[r] + (double)smp_g(sample(r), kSmpShiftG3, B), q, qinv)),
+                                      dst1 + tid + T * r);
+        }
+        continue;
+      }
 #pragma unroll 1
       for (int poly = 0; poly < 2; poly++) {
         if (poly == 1) {
@@ -151,7 +181,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 #pragma unroll
           for (int r = 0; r < R; r++) {
             const int j = tid + T * r;
-            add[r] = (double)smp_g(sample(r), poly == 0 ? 8 : 16, B);
+            add[r] = (double)smp_g(sample(r), poly == 0 ? kSmpShiftG2 : kSmpShiftG3, B);
             if (poly == 0) {
               add[r] += __builtin_rint(value * dt.enc_T[j]);
               if (BRIGHT) add[r] += __builtin_rint(fb * dt.cosj[j]);
@@ -179,7 +209,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
   uint64_t *cdt = reinterpret_cast<uint64_t *>(lds + S::SLOTS);
-  uint32_t *lds32 = reinterpret_cast<uint32_t *>(lds);
+  uint16_t *lds16 = reinterpret_cast<uint16_t *>(lds);
   const int tid = threadIdx.x;
   for (int i = tid; i < kCdtSlots; i += T) cdt[i] = dt.cdt[i];
   __syncthreads();
@@ -188,7 +218,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   const uint64_t qi = lc.qi[l];
   uint32_t smp[R];
   // s from tag 16 (ternary), e from tag 17 (Gaussian); the third stream is unused
-  draw_samples<LOGN, LOGR>(smp, lds32, cdt, B, tid, k0, k1, 0, kTagSk, kTagEk, kTagEk);
+  draw_samples<LOGN, LOGR>(smp, lds16, cdt, B, tid, k0, k1, 0, kTagSk, kTagEk, kTagEk);
   // a_l: uniform residues by rejection, coefficient j tries block j, then N + j, ...
   // accept w < q * floor(2^64 / q) = 2^64 - (2^64 mod q)
   const uint64_t limit = 0ULL - ((~0ULL % qi + 1) % qi);
@@ -231,7 +261,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   uint64_t *pk0 = dt.pk + (size_t)l * N;
 #pragma unroll
   for (int r = 0; r < R; r++) {
-    const double e = (double)smp_g(smp[r], 8, B);
+    const double e = (double)smp_g(smp[r], kSmpShiftG2, B);
     pk0[tid + T * r] = (uint64_t)canon(e - a[r], q, qinv);
   }
 }

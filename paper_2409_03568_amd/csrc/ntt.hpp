@@ -296,6 +296,45 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
   }
 }
 
+// The same stages applied to two arrays with the same factors (two independent
+// butterfly chains the scheduler can interleave).
+template <int LOGN, int LOGR, int PASS, uint32_t RED>
+CKKS_HD void inv_pass2(double (&x)[1 << LOGR], double (&x2)[1 << LOGR], int tid_in, const double *__restrict__ itw,
+                      const PassTw<LOGN, LOGR, PASS> &regs, double q, double qinv) {
+  const int tid = opaque(tid_in);
+  using S = NttShape<LOGN, LOGR>;
+  using PT = PassTw<LOGN, LOGR, PASS>;
+  constexpr int S0 = S::start(PASS), P = S::len(PASS), G = S::R >> P;
+  constexpr int LTLO = LOGN - S0 - P;
+#pragma unroll
+  for (int u = 0; u < G; u++) {
+    const unsigned g = (unsigned)tid + (unsigned)S::T * u;
+    const unsigned blk = PASS == 0 ? 0u : g >> LTLO;
+#pragma unroll
+    for (int l = P - 1; l >= 0; l--) {
+      const int s = S0 + l;
+      const int half = 1 << (P - 1 - l);
+#pragma unroll
+      for (int k = 0; k < (1 << P); k++) {
+        if (k & half) continue;
+        const unsigned t = (unsigned)(k >> (P - l));
+        double W;
+        if constexpr (PT::kPrefetch)
+          W = regs.w[u * PT::PER + (1 << l) - 1 + t];
+        else
+          W = itw[(1u << s) + (blk << l) + t];
+        gs_butterfly(x[k * G + u], x[(k + half) * G + u], W, q, qinv);
+        gs_butterfly(x2[k * G + u], x2[(k + half) * G + u], W, q, qinv);
+        if ((RED >> s) & 1u) {
+          x[k * G + u] = reduce(x[k * G + u], q, qinv);
+          x2[k * G + u] = reduce(x2[k * G + u], q, qinv);
+        }
+      }
+      stage_fence();
+    }
+  }
+}
+
 // The element index is the bitwise OR of a thread part, elem_index(tid, 0), and a
 // register part, elem_index(0, r), on disjoint bits (the thread index and the register
 // index fill different bit fields of it), so each thread computes one base slot per
@@ -422,6 +461,40 @@ template <int LOGN, int LOGR, uint32_t RED>
 __device__ __forceinline__ void ntt_inverse(double (&x)[1 << LOGR], double *lds, int tid, const double *__restrict__ itw,
                                             double q, double qinv) {
   ntt_inverse<LOGN, LOGR, RED>(x, lds, tid, itw, q, qinv, [] {});
+}
+
+// Two inverse transforms with the same prime at once: one set of exchanges (x through
+// lds, x2 through lds2, each N slots), shared twiddle loads and barriers.
+template <int LOGN, int LOGR, uint32_t RED, int PASS, class F>
+__device__ __forceinline__ void inv_rest2(double (&x)[1 << LOGR], double (&x2)[1 << LOGR], double *lds, double *lds2,
+                                          int tid, const double *__restrict__ itw, double q, double qinv,
+                                          F &&before_last) {
+  if constexpr (PASS >= 0) {
+    using NS = NttShape<LOGN, LOGR>;
+    constexpr bool kLocal = NS::same_wave_sets(PASS + 1, PASS);
+    PassTw<LOGN, LOGR, PASS> w;
+    tw_prefetch<LOGN, LOGR, PASS>(w, tid, itw);
+    if constexpr (PASS == 0) before_last();
+    exchange_lead<kLocal, PASS == NS::NPASS - 2>();
+    lds_store<LOGN, LOGR, PASS + 1>(lds, x, tid);
+    lds_store<LOGN, LOGR, PASS + 1>(lds2, x2, tid);
+    exchange_mid<kLocal>();
+    lds_load<LOGN, LOGR, PASS>(lds, x, tid);
+    lds_load<LOGN, LOGR, PASS>(lds2, x2, tid);
+    inv_pass2<LOGN, LOGR, PASS, RED>(x, x2, tid, itw, w, q, qinv);
+    inv_rest2<LOGN, LOGR, RED, PASS - 1>(x, x2, lds, lds2, tid, itw, q, qinv, before_last);
+  }
+}
+
+template <int LOGN, int LOGR, uint32_t RED, class F>
+__device__ __forceinline__ void ntt_inverse2(double (&x)[1 << LOGR], double (&x2)[1 << LOGR], double *lds,
+                                             double *lds2, int tid, const double *__restrict__ itw, double q,
+                                             double qinv, F &&before_last) {
+  constexpr int LAST = NttShape<LOGN, LOGR>::NPASS - 1;
+  PassTw<LOGN, LOGR, LAST> w;
+  tw_prefetch<LOGN, LOGR, LAST>(w, tid, itw);
+  inv_pass2<LOGN, LOGR, LAST, RED>(x, x2, tid, itw, w, q, qinv);
+  inv_rest2<LOGN, LOGR, RED, LAST - 1>(x, x2, lds, lds2, tid, itw, q, qinv, before_last);
 }
 
 }  // namespace ckks

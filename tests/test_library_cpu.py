@@ -81,7 +81,7 @@ def test_parameter_validation(pkg, oracle_mod):
     assert code(log_scale=54) == -1  # 256 * 2^(54+1-13) = 2^50: pixel coefficients would not fit below q
     assert code(log_scale=52) == 0
     assert code(sigma=-1.0) == -1
-    assert code(gauss_bound=65) == -1
+    assert code(gauss_bound=64) == -1
     good = oracle_mod.gen_primes(13, 50, 6)
     assert code(primes=good[2:6]) == 0
     assert code(primes=[good[0], good[0], good[1], good[2]]) == -1  # repeated
