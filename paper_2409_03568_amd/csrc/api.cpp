@@ -135,7 +135,7 @@ static uint64_t ws_align(uint64_t x) { return (x + 255) / 256 * 256; }
 
 uint64_t cached_ws_bytes(const ckks_cache *cache, uint64_t n) {
   if (cache->kind == CKKS_CACHE_RADIX) return ws_align(n * kMaxDigits * sizeof(int16_t)) + 256;
-  return 3 * ws_align(n * sizeof(uint32_t)) + ws_align((2 + (uint64_t)cache->pool) * sizeof(uint32_t));
+  return 3 * ws_align(n * sizeof(uint32_t)) + ws_align((2 + (uint64_t)value_buckets(cache)) * sizeof(uint32_t));
 }
 
 hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *px, uint64_t n,

@@ -53,7 +53,7 @@ struct ckks_batch_plan {
   uint32_t *meta = nullptr;      // [chunk]
   uint32_t *miss = nullptr;      // [chunk]
   uint32_t *hits = nullptr;      // [chunk]
-  uint32_t *counters = nullptr;  // [2 + pool]
+  uint32_t *counters = nullptr;  // [2 + pool * slots]
   uint64_t *seg_end = nullptr;   // [seg_cap]
   double *seg_b = nullptr;       // [seg_cap]
   uint32_t seg_cap = 0;
@@ -141,7 +141,7 @@ int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_ba
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->miss), chunk * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->hits), chunk * sizeof(uint32_t));
   if (e == hipSuccess)
-    e = hipMalloc(reinterpret_cast<void **>(&p->counters), (2 + (size_t)(cache ? cache->pool : 0)) * sizeof(uint32_t));
+    e = hipMalloc(reinterpret_cast<void **>(&p->counters), (2 + (size_t)(cache ? value_buckets(cache) : 0)) * sizeof(uint32_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     free_plan(p);

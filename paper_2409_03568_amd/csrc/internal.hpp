@@ -103,6 +103,7 @@ struct ckks_ctx {
   hipMemPool_t pool = nullptr;  // stream-ordered scratch that keeps its memory between calls
 };
 
+
 struct ckks_cache {
   ckks_ctx *ctx = nullptr;
   int device = 0;
@@ -116,6 +117,14 @@ struct ckks_cache {
   uint64_t *ts = nullptr;         // [n_slots] Philox index of each entry
   uint32_t *count = nullptr;      // device: number of valid entries
 };
+
+// Hit buckets of value-cached encryption: one per (pool member, cache slot) pair while
+// there are at most 65,536 of them (the single-workgroup scan stays short), else one
+// per pool member.
+inline uint32_t value_slot_buckets(const ckks_cache *cache) {
+  return (uint64_t)cache->pool * cache->n_slots <= 65536 ? cache->n_slots : 1u;
+}
+inline uint32_t value_buckets(const ckks_cache *cache) { return cache->pool * value_slot_buckets(cache); }
 
 namespace ckks {
 

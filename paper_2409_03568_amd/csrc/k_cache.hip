@@ -56,10 +56,11 @@ __global__ void __launch_bounds__(256)
 
 // Per pixel t: meta = (slot + 1) | u << 16 for a cached value, with pool member
 // u = floor(npool * w / 2^64) from auxiliary word 0; 0 for a value that is not cached,
-// whose index is appended to the miss list.  Hits are counted per pool member.
+// whose index is appended to the miss list.  Hits are counted per bucket u * nslots +
+// slot (nslots = 1: per pool member).
 __global__ void __launch_bounds__(kThreads)
     k_value_meta(const uint8_t *__restrict__ px, uint64_t n, uint64_t first_index, uint64_t s0, uint64_t s1,
-                 const int16_t *__restrict__ slot_of, uint32_t npool, uint32_t *__restrict__ meta,
+                 const int16_t *__restrict__ slot_of, uint32_t npool, uint32_t nslots, uint32_t *__restrict__ meta,
                  uint32_t *__restrict__ miss_list, uint32_t *miss_count, uint32_t *__restrict__ ucount) {
   for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
     const int slot = slot_of[px[t]];
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(kThreads)
       const uint64_t w = philox4x64_10(first_index + t, kTagAux, 0, 0, s0, s1).w[0];
       const uint32_t u = (uint32_t)mulhi64(w, npool);
       meta[t] = (uint32_t)(slot + 1) | (u << 16);
-      atomicAdd(&ucount[u], 1u);
+      atomicAdd(&ucount[u * nslots + (nslots > 1 ? (uint32_t)slot : 0u)], 1u);
     } else {
       meta[t] = 0;
       miss_list[atomicAdd(miss_count, 1u)] = (uint32_t)t;
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// Exclusive prefix sum of the per-member hit counts (in place: they become the bucket
+// Exclusive prefix sum of the per-bucket hit counts (in place: they become the bucket
 // cursors) and the total hit count.  One workgroup of kScanThreads threads.
 constexpr int kScanThreads = 1024;
 __global__ void __launch_bounds__(kScanThreads) k_bucket_scan(uint32_t *__restrict__ ucount, uint32_t npool,
@@ -102,14 +103,15 @@ __global__ void __launch_bounds__(kScanThreads) k_bucket_scan(uint32_t *__restri
   if (threadIdx.x == kScanThreads - 1) *total = part[kScanThreads - 1];
 }
 
-// Hit pixels grouped by pool member (order inside a group is arbitrary; every output row
-// is written independently, so the result does not depend on it).
+// Hit pixels grouped by pool member and, within a member, by cache slot (order inside a
+// bucket is arbitrary; every output row is written independently, so the result does
+// not depend on it).
 __global__ void __launch_bounds__(kThreads)
-    k_value_scatter(const uint32_t *__restrict__ meta, uint64_t n, uint32_t *__restrict__ cursor,
+    k_value_scatter(const uint32_t *__restrict__ meta, uint64_t n, uint32_t nslots, uint32_t *__restrict__ cursor,
                     uint32_t *__restrict__ hits) {
   for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t m = meta[t];
-    if (m != 0) hits[atomicAdd(&cursor[m >> 16], 1u)] = (uint32_t)t;
+    if (m != 0) hits[atomicAdd(&cursor[(m >> 16) * nslots + (nslots > 1 ? (m & 0xffffu) - 1u : 0u)], 1u)] = (uint32_t)t;
   }
 }
 
@@ -277,12 +279,14 @@ hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const u
                              uint32_t *miss_list, uint32_t *counters, uint32_t *hits, hipStream_t st) {
   (void)c;
   uint32_t *miss_count = counters, *hit_count = counters + 1, *ucount = counters + 2;
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 + cache->pool, kThreads)), dim3(kThreads), 0, st, counters,
-                     2u + cache->pool, 0u);
+  const uint32_t nb = value_buckets(cache);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 + nb, kThreads)), dim3(kThreads), 0, st, counters, 2u + nb, 0u);
   hipLaunchKernelGGL(k_value_meta, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, px, n, first_index, seed0,
-                     seed1, cache->slot_of, cache->pool, meta, miss_list, miss_count, ucount);
-  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanThreads), 0, st, ucount, cache->pool, hit_count);
-  hipLaunchKernelGGL(k_value_scatter, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, meta, n, ucount, hits);
+                     seed1, cache->slot_of, cache->pool, value_slot_buckets(cache), meta, miss_list, miss_count,
+                     ucount);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanThreads), 0, st, ucount, nb, hit_count);
+  hipLaunchKernelGGL(k_value_scatter, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, meta, n,
+                     value_slot_buckets(cache), ucount, hits);
   return hipGetLastError();
 }
 
