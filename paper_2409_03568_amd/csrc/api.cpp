@@ -263,11 +263,11 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
   }
   // the transforms' lazy-reduction schedule is compiled per class of prime sizes
   c->rc = qmax < 1099511627776.0 ? 0 : 1;
-  // values per NTT thread (measured on MI355X at N = 8192): encryption is fastest with 8
-  // (16 waves per ciphertext at 127 VGPRs, 4 waves per SIMD), decryption with 16 (two
-  // 8-wave workgroups per CU); 8 needs N / 8 <= 1024 threads
+  // values per NTT thread (measured on MI355X at N = 8192): encryption, decryption and
+  // the product are fastest with 8 (16 waves per ciphertext, 4 waves per SIMD); 8 needs
+  // N / 8 <= 1024 threads
   c->logr_enc = N / 8 <= 1024 ? 3 : 4;
-  c->logr_dec = 4;
+  c->logr_dec = c->logr_enc;
   c->logr_mul = c->logr_enc;
   hipError_t e = hipSuccess;
   DevTables &d = c->dev;
