@@ -54,10 +54,20 @@ __global__ void __launch_bounds__(256)
   if (v == 0) *count = nz < k ? nz : k;
 }
 
+// Bucket of a hit with pool member u and cache slot: pool members are taken in groups of
+// kPoolGroup, and within a group the order is slot-major, so a stretch of the hit list
+// touches a few pool entries and few value entries at a time (both stay in L2).  With
+// nslots = 1 the bucket is the pool member.
+constexpr uint32_t kPoolGroup = 4;
+__device__ __forceinline__ uint32_t hit_bucket(uint32_t u, uint32_t slot, uint32_t nslots, uint32_t npool) {
+  if (nslots == 1) return u;
+  const uint32_t g0 = u - u % kPoolGroup, gsz = min(kPoolGroup, npool - g0);
+  return g0 * nslots + slot * gsz + (u - g0);
+}
+
 // Per pixel t: meta = (slot + 1) | u << 16 for a cached value, with pool member
 // u = floor(npool * w / 2^64) from auxiliary word 0; 0 for a value that is not cached,
-// whose index is appended to the miss list.  Hits are counted per bucket u * nslots +
-// slot (nslots = 1: per pool member).
+// whose index is appended to the miss list.  Hits are counted per bucket (hit_bucket).
 __global__ void __launch_bounds__(kThreads)
     k_value_meta(const uint8_t *__restrict__ px, uint64_t n, uint64_t first_index, uint64_t s0, uint64_t s1,
                  const int16_t *__restrict__ slot_of, uint32_t npool, uint32_t nslots, uint32_t *__restrict__ meta,
@@ -68,7 +78,7 @@ __global__ void __launch_bounds__(kThreads)
       const uint64_t w = philox4x64_10(first_index + t, kTagAux, 0, 0, s0, s1).w[0];
       const uint32_t u = (uint32_t)mulhi64(w, npool);
       meta[t] = (uint32_t)(slot + 1) | (u << 16);
-      atomicAdd(&ucount[u * nslots + (nslots > 1 ? (uint32_t)slot : 0u)], 1u);
+      atomicAdd(&ucount[hit_bucket(u, (uint32_t)slot, nslots, npool)], 1u);
     } else {
       meta[t] = 0;
       miss_list[atomicAdd(miss_count, 1u)] = (uint32_t)t;
@@ -103,15 +113,14 @@ __global__ void __launch_bounds__(kScanThreads) k_bucket_scan(uint32_t *__restri
   if (threadIdx.x == kScanThreads - 1) *total = part[kScanThreads - 1];
 }
 
-// Hit pixels grouped by pool member and, within a member, by cache slot (order inside a
-// bucket is arbitrary; every output row is written independently, so the result does
-// not depend on it).
+// Hit pixels grouped by bucket (order inside a bucket is arbitrary; every output row is
+// written independently, so the result does not depend on it).
 __global__ void __launch_bounds__(kThreads)
-    k_value_scatter(const uint32_t *__restrict__ meta, uint64_t n, uint32_t nslots, uint32_t *__restrict__ cursor,
-                    uint32_t *__restrict__ hits) {
+    k_value_scatter(const uint32_t *__restrict__ meta, uint64_t n, uint32_t nslots, uint32_t npool,
+                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ hits) {
   for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t m = meta[t];
-    if (m != 0) hits[atomicAdd(&cursor[(m >> 16) * nslots + (nslots > 1 ? (m & 0xffffu) - 1u : 0u)], 1u)] = (uint32_t)t;
+    if (m != 0) hits[atomicAdd(&cursor[hit_bucket(m >> 16, (m & 0xffffu) - 1u, nslots, npool)], 1u)] = (uint32_t)t;
   }
 }
 
@@ -286,7 +295,7 @@ hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const u
                      ucount);
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanThreads), 0, st, ucount, nb, hit_count);
   hipLaunchKernelGGL(k_value_scatter, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, meta, n,
-                     value_slot_buckets(cache), ucount, hits);
+                     value_slot_buckets(cache), cache->pool, ucount, hits);
   return hipGetLastError();
 }
 
