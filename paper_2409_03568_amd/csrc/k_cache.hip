@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(256)
 // kPoolGroup, and within a group the order is slot-major, so a stretch of the hit list
 // touches a few pool entries and few value entries at a time (both stay in L2).  With
 // nslots = 1 the bucket is the pool member.
-constexpr uint32_t kPoolGroup = 4;
+constexpr uint32_t kPoolGroup = 2;
 __device__ __forceinline__ uint32_t hit_bucket(uint32_t u, uint32_t slot, uint32_t nslots, uint32_t npool) {
   if (nslots == 1) return u;
   const uint32_t g0 = u - u % kPoolGroup, gsz = min(kPoolGroup, npool - g0);
