@@ -133,10 +133,12 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out);
 /* Wait for all work of the context and free it.  NULL is ignored. */
 void ckks_context_destroy(ckks_ctx *ctx);
 
-/* Tuning of the NTT kernels (encryption, decryption, keys): each thread of a workgroup
- * holds values_per_thread ring coefficients (8, 16 or 32), so a workgroup has
- * N / values_per_thread threads (at most 1024: 8 needs N <= 8192).  Results are
- * identical for every setting; only speed differs.  CKKS_EINVAL for other values. */
+/* Tuning of the NTT kernels (encryption, decryption, keys, ciphertext product): each
+ * thread of a workgroup holds values_per_thread ring coefficients (8, 16 or 32), so a
+ * workgroup has N / values_per_thread threads (at most 1024: 8 needs N <= 8192).  The
+ * setter applies to all of them (ckks_autotune chooses per kernel); the getter reports
+ * the encryption kernel's.  Results are identical for every setting; only speed differs.
+ * CKKS_EINVAL for other values.  The default is 8 where allowed, else 16. */
 int ckks_context_set_ntt_width(ckks_ctx *ctx, uint32_t values_per_thread);
 int ckks_context_get_ntt_width(const ckks_ctx *ctx, uint32_t *values_per_thread);
 
