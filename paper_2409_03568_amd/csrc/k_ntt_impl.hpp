@@ -143,8 +143,8 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 #pragma unroll
         for (int r = 0; r < R; r++) {
           const unsigned e = elem_index<LOGN, LOGR, S::LAST>(tid, r);
-          y[r] = mulmod(x[r], pk0[e], q, qinv);
-          y1[r] = mulmod(x[r], pk1[e], q, qinv);
+          y[r] = mulmod(x[r], ld_table(pk0, e), q, qinv);
+          y1[r] = mulmod(x[r], ld_table(pk1, e), q, qinv);
         }
       }
       if constexpr (S::kDual) {
@@ -156,16 +156,18 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 #pragma unroll
           for (int r = 0; r < R; r++) {
             const int j = tid + T * r;
-            add[r] = (double)smp_g(sample(r), kSmpShiftG2, B) + __builtin_rint(value * dt.enc_T[j]);
-            if (BRIGHT) add[r] += __builtin_rint(fb * dt.cosj[j]);
+            add[r] = (double)smp_g(sample(r), kSmpShiftG2, B) + __builtin_rint(value * ld_table(dt.enc_T, j));
+            if (BRIGHT) add[r] += __builtin_rint(fb * ld_table(dt.cosj, j));
           }
         });
         uint64_t *dst0 = out + (size_t)l * N, *dst1 = out + ((size_t)L + l) * N;
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), dst0 + tid + T * r);
+          const unsigned off = ((unsigned)tid + (unsigned)T * r) << 3;  // 32-bit byte offset
+          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)),
+                                      reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(dst0) + off));
           __builtin_nontemporal_store(f64_to_u64(canon(y1[r] + (double)smp_g(sample(r), kSmpShiftG3, B), q, qinv)),
-                                      dst1 + tid + T * r);
+                                      reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(dst1) + off));
         }
         continue;
       }
@@ -183,8 +185,8 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
             const int j = tid + T * r;
             add[r] = (double)smp_g(sample(r), poly == 0 ? kSmpShiftG2 : kSmpShiftG3, B);
             if (poly == 0) {
-              add[r] += __builtin_rint(value * dt.enc_T[j]);
-              if (BRIGHT) add[r] += __builtin_rint(fb * dt.cosj[j]);
+              add[r] += __builtin_rint(value * ld_table(dt.enc_T, j));
+              if (BRIGHT) add[r] += __builtin_rint(fb * ld_table(dt.cosj, j));
             }
           }
         });
@@ -332,7 +334,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     for (int r = 0; r < R; r++) x[r] = u64_to_f64(__builtin_nontemporal_load(c1 + tid + T * r));
     ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd, q, qinv);
 #pragma unroll
-    for (int r = 0; r < R; r++) x[r] = mulmod(x[r], dt.s_hat[elem_index<LOGN, LOGR, S::LAST>(tid, r)], q, qinv);
+    for (int r = 0; r < R; r++) x[r] = mulmod(x[r], ld_table(dt.s_hat, elem_index<LOGN, LOGR, S::LAST>(tid, r)), q, qinv);
     // c0 is loaded from HBM before the final exchange of the transform
     uint64_t c0w[R];
     ntt_inverse<LOGN, LOGR, Red::inv>(x, lds, tid, dt.tw_inv, q, qinv, [&] {
@@ -343,7 +345,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const double d = center(x[r] + u64_to_f64(c0w[r]), q, qinv);
-      acc = __builtin_fma(d, dt.cosj[tid + T * r], acc);
+      acc = __builtin_fma(d, ld_table(dt.cosj, tid + T * r), acc);
     }
     // workgroup sum in a fixed order: wave butterflies, then the waves in sequence
 #pragma unroll

@@ -167,6 +167,13 @@ CKKS_HD unsigned lds_slot(unsigned tb, unsigned pr) { return (tb ^ (pr & 15u)) +
 // ---------------------------------------------------------------------------
 // passes
 // ---------------------------------------------------------------------------
+// Element idx of a table whose base is the same for the whole launch: the byte offset is
+// a 32-bit value, so the load can take the base from scalar registers and the offset from
+// one vector register instead of building a 64-bit address per load.
+CKKS_HD double ld_table(const double *__restrict__ base, unsigned idx) {
+  return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + (idx << 3));
+}
+
 // The thread index as a value the compiler cannot prove loop-invariant: address
 // arithmetic derived from it stays next to its use instead of being hoisted out of the
 // per-ciphertext loops, where dozens of precomputed pointers would stay live.
@@ -216,7 +223,8 @@ CKKS_HD void tw_prefetch(PassTw<LOGN, LOGR, PASS> &regs, int tid_in, const doubl
 #pragma unroll
       for (int l = 0; l < P; l++)
 #pragma unroll
-        for (int t = 0; t < (1 << l); t++) w[u * PT::PER + (1 << l) - 1 + t] = tw[(1u << (S0 + l)) + (blk << l) + t];
+        for (int t = 0; t < (1 << l); t++)
+          w[u * PT::PER + (1 << l) - 1 + t] = ld_table(tw, (1u << (S0 + l)) + (blk << l) + t);
     }
   }
 }
@@ -247,7 +255,7 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
         if constexpr (PT::kPrefetch)
           W = regs.w[u * PT::PER + (1 << l) - 1 + t];
         else
-          W = tw[(1u << s) + (blk << l) + t];
+          W = ld_table(tw, (1u << s) + (blk << l) + t);
         ct_butterfly(x[k * G + u], x[(k + half) * G + u], W, q, qinv);
       }
       if ((RED >> s) & 1u) {
@@ -285,7 +293,7 @@ CKKS_HD void inv_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
         if constexpr (PT::kPrefetch)
           W = regs.w[u * PT::PER + (1 << l) - 1 + t];
         else
-          W = itw[(1u << s) + (blk << l) + t];
+          W = ld_table(itw, (1u << s) + (blk << l) + t);
         double &X = x[k * G + u];
         double &Y = x[(k + half) * G + u];
         gs_butterfly(X, Y, W, q, qinv);
@@ -322,7 +330,7 @@ CKKS_HD void inv_pass2(double (&x)[1 << LOGR], double (&x2)[1 << LOGR], int tid_
         if constexpr (PT::kPrefetch)
           W = regs.w[u * PT::PER + (1 << l) - 1 + t];
         else
-          W = itw[(1u << s) + (blk << l) + t];
+          W = ld_table(itw, (1u << s) + (blk << l) + t);
         gs_butterfly(x[k * G + u], x[(k + half) * G + u], W, q, qinv);
         gs_butterfly(x2[k * G + u], x2[(k + half) * G + u], W, q, qinv);
         if ((RED >> s) & 1u) {
