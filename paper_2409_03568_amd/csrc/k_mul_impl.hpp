@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   // special-prime accumulators
   uint64_t *d2s = scratch + (uint64_t)blockIdx.x * (uint64_t)(2 * level + 2) * N;
   uint64_t *own = d2s + (size_t)level * N;
-  double *accP = reinterpret_cast<double *>(d2s + (size_t)2 * level * N);
+  uint64_t *accw = d2s + (size_t)2 * level * N;  // bit patterns of doubles
   for (uint64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const uint64_t *a = A + it * S_ct, *b = Bc + it * S_ct;
     uint64_t *o = out + it * S_ct;
@@ -148,45 +148,49 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       // three transforms live at a time: a1 b0 waits in this limb's own-prime scratch row
       // until b1 arrives (not in out, which may be b)
       uint64_t *o0 = o + (size_t)j * N, *o1 = o + ((size_t)level + j) * N;
+      const uint64_t *a0 = a + (size_t)j * N, *b0 = b + (size_t)j * N;
+      const uint64_t *a1 = a + ((size_t)level + j) * N, *b1 = b + ((size_t)level + j) * N;
+      uint64_t *ownj = own + (size_t)j * N, *d2j = d2s + (size_t)j * N;
       double x[R], y[R], z[R];
 #pragma unroll
-      for (int r = 0; r < R; r++) x[r] = u64_to_f64(a[(size_t)j * N + tid + T * r]);
+      for (int r = 0; r < R; r++) x[r] = u64_to_f64(ld_word(a0, tid + T * r));
       ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, tw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
         x[r] = reduce(mulmod(x[r], ninv, q, qinv), q, qinv);  // a0 (the a side carries N^-1)
-        y[r] = u64_to_f64(b[(size_t)j * N + tid + T * r]);
+        y[r] = u64_to_f64(ld_word(b0, tid + T * r));
       }
       ntt_forward<LOGN, LOGR, Red::fwd_big>(y, lds, tid, tw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
         y[r] = reduce(y[r], q, qinv);  // b0
-        o0[tid + T * r] = __builtin_bit_cast(uint64_t, mulmod(x[r], y[r], q, qinv));  // d0
-        z[r] = u64_to_f64(a[((size_t)level + j) * N + tid + T * r]);
+        st_word(o0, tid + T * r, __builtin_bit_cast(uint64_t, mulmod(x[r], y[r], q, qinv)));  // d0
+        z[r] = u64_to_f64(ld_word(a1, tid + T * r));
       }
       ntt_forward<LOGN, LOGR, Red::fwd_big>(z, lds, tid, tw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
         z[r] = reduce(z[r], q, qinv);  // a1 without N^-1
-        const double a1 = reduce(mulmod(z[r], ninv, q, qinv), q, qinv);
-        own[(size_t)j * N + tid + T * r] = __builtin_bit_cast(uint64_t, mulmod(a1, y[r], q, qinv));  // a1 b0
-        y[r] = u64_to_f64(b[((size_t)level + j) * N + tid + T * r]);
+        const double a1n = reduce(mulmod(z[r], ninv, q, qinv), q, qinv);
+        st_word(ownj, tid + T * r, __builtin_bit_cast(uint64_t, mulmod(a1n, y[r], q, qinv)));  // a1 b0
+        y[r] = u64_to_f64(ld_word(b1, tid + T * r));
       }
       ntt_forward<LOGN, LOGR, Red::fwd_big>(y, lds, tid, tw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        const int c = tid + T * r;
-        const double b1 = reduce(y[r], q, qinv);
-        o1[c] = __builtin_bit_cast(
-            uint64_t, reduce(mulmod(x[r], b1, q, qinv) + __builtin_bit_cast(double, own[(size_t)j * N + c]), q,
-                             qinv));  // d1
+        const unsigned c = tid + T * r;
+        const double b1h = reduce(y[r], q, qinv);
+        st_word(o1, c,
+                __builtin_bit_cast(uint64_t, reduce(mulmod(x[r], b1h, q, qinv) +
+                                                        __builtin_bit_cast(double, ld_word(ownj, c)),
+                                                    q, qinv)));  // d1
         // NTT(d2) for the key product in prime j (keys carry N^-1), and d2 itself
-        own[(size_t)j * N + c] = __builtin_bit_cast(uint64_t, mulmod(z[r], b1, q, qinv));
-        y[r] = mulmod(reduce(mulmod(z[r], ninv, q, qinv), q, qinv), b1, q, qinv);
+        st_word(ownj, c, __builtin_bit_cast(uint64_t, mulmod(z[r], b1h, q, qinv)));
+        y[r] = mulmod(reduce(mulmod(z[r], ninv, q, qinv), q, qinv), b1h, q, qinv);
       }
       ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, itw, q, qinv);
 #pragma unroll
-      for (int r = 0; r < R; r++) d2s[(size_t)j * N + tid + T * r] = f64_to_u64(canon(y[r], q, qinv));
+      for (int r = 0; r < R; r++) st_word(d2j, tid + T * r, f64_to_u64(canon(y[r], q, qinv)));
     }
     // 2 + 3. key switching, the special prime (index L) first
     for (int jj = 0; jj <= level; jj++) {
@@ -200,19 +204,21 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       for (int i = 0; i < level; i++) {
         double x[R];
         if (i == j) {
+          const uint64_t *owni = own + (size_t)i * N;
 #pragma unroll
-          for (int r = 0; r < R; r++) x[r] = __builtin_bit_cast(double, own[(size_t)i * N + tid + T * r]);
+          for (int r = 0; r < R; r++) x[r] = __builtin_bit_cast(double, ld_word(owni, tid + T * r));
         } else {
+          const uint64_t *d2i = d2s + (size_t)i * N;
 #pragma unroll
-          for (int r = 0; r < R; r++) x[r] = reduce(u64_to_f64(d2s[(size_t)i * N + tid + T * r]), q, qinv);
+          for (int r = 0; r < R; r++) x[r] = reduce(u64_to_f64(ld_word(d2i, tid + T * r)), q, qinv);
           ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, tw, q, qinv);
         }
         const double *kb = dt.evk_hat + (((size_t)i * (L + 1) + j) * 2) * N, *ka = kb + N;
 #pragma unroll
         for (int r = 0; r < R; r++) {
           const unsigned e = elem_index<LOGN, LOGR, S::LAST>(tid, r);
-          c0[r] = reduce(c0[r] + mulmod(x[r], kb[e], q, qinv), q, qinv);
-          c1[r] = reduce(c1[r] + mulmod(x[r], ka[e], q, qinv), q, qinv);
+          c0[r] = reduce(c0[r] + mulmod(x[r], ld_table(kb, e), q, qinv), q, qinv);
+          c1[r] = reduce(c1[r] + mulmod(x[r], ld_table(ka, e), q, qinv), q, qinv);
         }
       }
       if (jj == 0) {
@@ -220,8 +226,9 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
         ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          accP[tid + T * r] = center(c0[r], q, qinv);
-          accP[N + tid + T * r] = center(c1[r], q, qinv);
+          const unsigned c = tid + T * r;
+          st_word(accw, c, __builtin_bit_cast(uint64_t, center(c0[r], q, qinv)));
+          st_word(accw, N + c, __builtin_bit_cast(uint64_t, center(c1[r], q, qinv)));
         }
         continue;
       }
@@ -229,17 +236,19 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       uint64_t *o0 = o + (size_t)j * N, *o1 = o + ((size_t)level + j) * N;
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        const int c = tid + T * r;
-        c0[r] = reduce(mulmod(c0[r], pinv, q, qinv) + __builtin_bit_cast(double, o0[c]), q, qinv);
-        c1[r] = reduce(mulmod(c1[r], pinv, q, qinv) + __builtin_bit_cast(double, o1[c]), q, qinv);
+        const unsigned c = tid + T * r;
+        c0[r] = reduce(mulmod(c0[r], pinv, q, qinv) + __builtin_bit_cast(double, ld_word(o0, c)), q, qinv);
+        c1[r] = reduce(mulmod(c1[r], pinv, q, qinv) + __builtin_bit_cast(double, ld_word(o1, c)), q, qinv);
       }
       ntt_inverse<LOGN, LOGR, Red::inv>(c0, lds, tid, itw, q, qinv);
       ntt_inverse<LOGN, LOGR, Red::inv>(c1, lds, tid, itw, q, qinv);
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        const int c = tid + T * r;
-        o0[c] = f64_to_u64(canon(c0[r] - mulmod(accP[c], pinv, q, qinv), q, qinv));
-        o1[c] = f64_to_u64(canon(c1[r] - mulmod(accP[N + c], pinv, q, qinv), q, qinv));
+        const unsigned c = tid + T * r;
+        const double p0 = __builtin_bit_cast(double, ld_word(accw, c));
+        const double p1 = __builtin_bit_cast(double, ld_word(accw, N + c));
+        st_word(o0, c, f64_to_u64(canon(c0[r] - mulmod(p0, pinv, q, qinv), q, qinv)));
+        st_word(o1, c, f64_to_u64(canon(c1[r] - mulmod(p1, pinv, q, qinv), q, qinv)));
       }
     }
   }

@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     const uint64_t *c1 = c0 + (size_t)level * N;
     double x[R];
 #pragma unroll
-    for (int r = 0; r < R; r++) x[r] = u64_to_f64(__builtin_nontemporal_load(c1 + tid + T * r));
+    for (int r = 0; r < R; r++) x[r] = u64_to_f64(__builtin_nontemporal_load(word_at(c1, tid + T * r)));
     ntt_forward<LOGN, LOGR, Red::fwd_big>(x, lds, tid, dt.tw_fwd, q, qinv);
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = mulmod(x[r], ld_table(dt.s_hat, elem_index<LOGN, LOGR, S::LAST>(tid, r)), q, qinv);
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     uint64_t c0w[R];
     ntt_inverse<LOGN, LOGR, Red::inv>(x, lds, tid, dt.tw_inv, q, qinv, [&] {
 #pragma unroll
-      for (int r = 0; r < R; r++) c0w[r] = __builtin_nontemporal_load(c0 + tid + T * r);
+      for (int r = 0; r < R; r++) c0w[r] = __builtin_nontemporal_load(word_at(c0, tid + T * r));
     });
     double acc = 0.0;
 #pragma unroll

@@ -174,6 +174,16 @@ CKKS_HD double ld_table(const double *__restrict__ base, unsigned idx) {
   return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + (idx << 3));
 }
 
+// The same for one row of 64-bit words (a limb of a ciphertext or of a scratch buffer):
+// the row's base is uniform, idx < 2^29.
+CKKS_HD const uint64_t *word_at(const uint64_t *base, unsigned idx) {
+  return reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(base) + (idx << 3));
+}
+CKKS_HD uint64_t ld_word(const uint64_t *base, unsigned idx) { return *word_at(base, idx); }
+CKKS_HD void st_word(uint64_t *base, unsigned idx, uint64_t v) {
+  *reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(base) + (idx << 3)) = v;
+}
+
 // The thread index as a value the compiler cannot prove loop-invariant: address
 // arithmetic derived from it stays next to its use instead of being hoisted out of the
 // per-ciphertext loops, where dozens of precomputed pointers would stay live.
