@@ -163,11 +163,10 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
         uint64_t *dst0 = out + (size_t)l * N, *dst1 = out + ((size_t)L + l) * N;
 #pragma unroll
         for (int r = 0; r < R; r++) {
-          const unsigned off = ((unsigned)tid + (unsigned)T * r) << 3;  // 32-bit byte offset
-          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)),
-                                      reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(dst0) + off));
+          const unsigned c = tid + T * r;
+          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), word_at(dst0, c));
           __builtin_nontemporal_store(f64_to_u64(canon(y1[r] + (double)smp_g(sample(r), kSmpShiftG3, B), q, qinv)),
-                                      reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(dst1) + off));
+                                      word_at(dst1, c));
         }
         continue;
       }
@@ -193,7 +192,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
         uint64_t *dst = out + ((size_t)poly * L + l) * N;
 #pragma unroll
         for (int r = 0; r < R; r++)
-          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), dst + tid + T * r);
+          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), word_at(dst, tid + T * r));
       }
     }
   }

@@ -179,10 +179,11 @@ CKKS_HD double ld_table(const double *__restrict__ base, unsigned idx) {
 CKKS_HD const uint64_t *word_at(const uint64_t *base, unsigned idx) {
   return reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(base) + (idx << 3));
 }
-CKKS_HD uint64_t ld_word(const uint64_t *base, unsigned idx) { return *word_at(base, idx); }
-CKKS_HD void st_word(uint64_t *base, unsigned idx, uint64_t v) {
-  *reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(base) + (idx << 3)) = v;
+CKKS_HD uint64_t *word_at(uint64_t *base, unsigned idx) {
+  return reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(base) + (idx << 3));
 }
+CKKS_HD uint64_t ld_word(const uint64_t *base, unsigned idx) { return *word_at(base, idx); }
+CKKS_HD void st_word(uint64_t *base, unsigned idx, uint64_t v) { *word_at(base, idx) = v; }
 
 // The thread index as a value the compiler cannot prove loop-invariant: address
 // arithmetic derived from it stays next to its use instead of being hoisted out of the
