@@ -25,6 +25,13 @@
  *  - Ciphertext layout (coefficient domain, canonical residues in [0, q_i)):
  *      data[ct][poly 0..1][limb 0..level-1][coefficient 0..N-1], uint64.
  *    A batch shares one level and one scale.
+ *  - Output descriptors: on input, out->count is 0 (the caller vouches for the buffer's
+ *    size) or the number of ciphertexts the buffer holds at level out->level (0 = the
+ *    result's level); a buffer with fewer bytes than the result needs is CKKS_EINVAL
+ *    before anything is enqueued.  On success count, level and scale describe the result.
+ *  - Keys: ckks_keygen and ckks_keys_import replace the keys of a context.  Key-switching
+ *    keys, caches, batch plans and servers made under the old keys are then invalid: the
+ *    product needs a new ckks_relin_keygen, and the others return CKKS_ESTATE.
  *  - Determinism: ciphertext t of an encryption call equals the result for pixel
  *    index first_index + t computed alone, bit for bit, whatever the batch size,
  *    stream or tiling: all randomness comes from Philox4x64-10 (Salmon et al.,
@@ -50,7 +57,8 @@ extern "C" {
 #define CKKS_ESCALE (-6)        /* operand scales differ */
 #define CKKS_ECACHE (-7)        /* cache kind / descriptor mismatch, or pixel not representable */
 #define CKKS_EUNSUPPORTED (-8)  /* parameter outside what the kernels implement */
-#define CKKS_ESTATE (-9)        /* keys not generated or imported yet */
+#define CKKS_ESTATE (-9)        /* keys not generated or imported yet, or replaced since */
+#define CKKS_PENDING 1          /* ckks_stream_status: work is still running (not an error) */
 
 typedef struct ckks_ctx ckks_ctx;
 typedef struct ckks_cache ckks_cache;
@@ -93,7 +101,10 @@ typedef struct ckks_ct_batch {
 #define CKKS_CACHE_VALUE_TOPK 2 /* scanning-based: the topk most frequent values of a scan image */
 #define CKKS_CACHE_VALUE_FULL 3 /* full caching: Enc(v) for every v in 0..255 */
 
-/* base, digits: radix caches (2 <= base <= 256, base^digits >= 256, base^(digits-1) <= 255).
+/* base, digits: radix caches (2 <= base <= 256, 2 <= digits <= 8, base^digits >= 256,
+ *              base^(digits-1) <= 255; one digit is refused: the radix randomness of
+ *              Sec. 3.3 draws one bit per radix above the lowest, so with a single digit
+ *              every pixel value would map to one fixed ciphertext).
  * topk:        VALUE_TOPK (1..256).
  * zero_pool:   VALUE_* caches: size n of the pool of encrypted zeros added to every cached
  *              pixel (Sec. 3.3 randomness pool), 1..4096.                                  */
@@ -207,6 +218,18 @@ int ckks_cache_entries(ckks_cache *cache, uint32_t *n_entries);
  * ckks_cache_entries (RADIX: entry 0 is Enc(0), entry 1+i is Enc(base^i)); host_pool
  * receives the zero_pool encrypted zeros of a value cache.  Any pointer may be NULL. */
 int ckks_cache_export(ckks_cache *cache, uint32_t *host_values, uint64_t *host_entries, uint64_t *host_pool);
+/* Install a cache built elsewhere -- full caching is prepared offline (Sec. 3.2), so a
+ * cache exported earlier (or computed by another implementation) can be loaded instead of
+ * rebuilt.  desc gives the kind and its parameters as for ckks_cache_build;
+ * host_values[n_entries] and host_entries[n_entries][2][L][N] are laid out as
+ * ckks_cache_export writes them (RADIX: n_entries = digits + 1 with values 0, 1, base, ...;
+ * VALUE_FULL: 256 entries with values 0..255; VALUE_TOPK: 1..topk distinct values);
+ * host_pool[zero_pool][2][L][N] holds a value cache's encrypted zeros (NULL for RADIX).
+ * The entries must be encryptions under the context's current keys (the library cannot
+ * check that); residues must be canonical (CKKS_EINVAL).  Synchronous: the data are
+ * copied to device memory owned by the new cache before the call returns. */
+int ckks_cache_import(ckks_ctx *ctx, const ckks_cache_desc *desc, uint32_t n_entries, const uint32_t *host_values,
+                      const uint64_t *host_entries, const uint64_t *host_pool, ckks_cache **out);
 
 /* Cached encryption of pixel d_px[t], index first_index + t, under the job seed:
  *  RADIX (Sec. 3.2 + 3.3): c = Enc(0) + sum_i d_i Enc(base^i) over the base-`base`
@@ -270,15 +293,23 @@ int ckks_mean_filter(ckks_ctx *ctx, const ckks_ct_batch *img, uint32_t H, uint32
 
 /* ---- decryption (Sec. 2.2.2) ---- */
 
-/* d_out[t] = slot 0 of decode(c0 + c1*s) for every ciphertext: sum_j x_j cos(pi j/N) / scale,
- * where x_j is the centered residue of limb 0.  Valid while every |x_j| < q_0/2, which
- * holds for pixel-sized messages at the supported parameters.  d_out is a device double[count]. */
+/* d_out[t] = slot 0 of decode(c0 + c1*s) (Sec. 2.2.2 decryption): sum_j x_j cos(pi j/N) / scale,
+ * where x_j is the centered integer of the decrypted coefficient j.  At level >= 2 x_j is
+ * the CRT lift of limbs 0 and 1, x_j = x0_j + q_0 k_j with x0_j centered mod q_0 and
+ * k_j = [(d1_j - x0_j) q_0^-1] centered mod q_1: exact while every |x_j| < q_0 q_1 / 2, so a
+ * coefficient past q_0/2 (a sum of a few hundred pixels at N = 4096, Delta = 2^30)
+ * still decodes correctly.  At level 1 only limb 0 exists: exact while |x_j| < q_0/2,
+ * which the library cannot check.  d_out is a device double[count]. */
 int ckks_decrypt_pixels(ckks_ctx *ctx, const ckks_ct_batch *in, double *d_out, void *stream);
 
 /* ---- streams ---- */
 
 /* Wait for all work enqueued on `stream` and report any asynchronous device error. */
 int ckks_stream_sync(ckks_ctx *ctx, void *stream);
+/* Non-blocking: CKKS_OK when all work enqueued on `stream` has completed, CKKS_PENDING (a
+ * positive value) while some is still running, CKKS_EDEVICE for an asynchronous device
+ * error. */
+int ckks_stream_status(ckks_ctx *ctx, void *stream);
 
 /* ---- autotuning ----
  * Times the NTT kernels (encryption, Sec. 2.2.2: one forward and two inverse
@@ -329,10 +360,17 @@ int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_ba
 /* d_px: n pixels (device).  host_seg_end: n_seg ascending image ends, the last = n.
  * host_seg_b: n_seg brightness constants, |b * scale * 2^(1 - log N)| < 2^50.
  * d_out: n doubles (device), the decrypted pixel + b values.  Ciphertext t uses Philox
- * index first_index + t.  Enqueued on `stream`. */
+ * index first_index + t.  cts_out (nullable): when given, its data (device memory for n
+ * ciphertexts of level L; count/level as for other outputs) receives every brightened
+ * ciphertext instead of the plan's ring buffer, and count/level/scale are set.
+ * Decryption decodes limb 0 when a worst-case bound on the coefficients of a pixel plus
+ * brightness (with the encryption errors bounded by the Gaussian tail cut) stays below
+ * q_0/2, as it does at every configured parameter set, else the two-limb lift of
+ * ckks_decrypt_pixels.  Enqueued on `stream`.  CKKS_ESTATE if the keys changed after the
+ * plan was made. */
 int ckks_batch_run(ckks_batch_plan *plan, const uint8_t *d_px, uint64_t n, const uint64_t *host_seg_end,
                    const double *host_seg_b, uint32_t n_seg, const uint64_t seed[2], uint64_t first_index,
-                   double *d_out, void *stream);
+                   double *d_out, ckks_ct_batch *cts_out, void *stream);
 
 void ckks_batch_plan_destroy(ckks_batch_plan *plan);
 

@@ -339,6 +339,33 @@ class Oracle:
             raise ArithmeticError("decryption bound violated (limb-0 lift disagrees with CRT)")
         return float(v)
 
+    def decrypt_exact(self, ct, level: int | None = None, scale: float | None = None) -> float:
+        """Decryption by its definition (Sec. 2.2.2), without the limb-0 shortcut: the residues
+        d_i = c0_i + c1_i s of every limb, their centered integer x in (-Q/2, Q/2] by the
+        Chinese remainder theorem over all `level` primes (Python integers), and slot 0 of
+        the decoding, sum_j x_j cos(pi j / N) / scale, summed exactly rounded (math.fsum)."""
+        import math
+
+        level = self.L if level is None else level
+        scale = self.scale if scale is None else scale
+        d = self.decrypt_coeffs(ct, level)
+        qs = self.q[:level]
+        Q = math.prod(qs)
+        x = [0] * self.N
+        for i, qi in enumerate(qs):
+            Mi = Q // qi
+            ci = Mi * pow(Mi % qi, -1, qi)
+            row = [int(v) for v in d[i]]
+            for j in range(self.N):
+                x[j] += row[j] * ci
+        terms = []
+        for j in range(self.N):
+            xj = x[j] % Q
+            if xj > Q // 2:
+                xj -= Q
+            terms.append(float(xj) * math.cos(math.pi * j / self.N))
+        return math.fsum(terms) / scale
+
     def decrypt_batch(self, cts, level: int | None = None, scale: float | None = None) -> np.ndarray:
         level = self.L if level is None else level
         scale = self.scale if scale is None else scale

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libckks_mi355x.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ckks_mi355x.h")
 
 CKKS_OK = 0
+CKKS_PENDING = 1
 ERRORS = {
     -1: "CKKS_EINVAL", -2: "CKKS_ENOMEM", -3: "CKKS_ENOMEM_BUDGET", -4: "CKKS_EDEVICE", -5: "CKKS_ELEVEL",
     -6: "CKKS_ESCALE", -7: "CKKS_ECACHE", -8: "CKKS_EUNSUPPORTED", -9: "CKKS_ESTATE",
@@ -110,6 +111,8 @@ _SIGS = {
     "ckks_cache_entries": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32)]),
     "ckks_cache_export": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_uint64)]),
+    "ckks_cache_import": (C.c_int, [C.c_void_p, C.POINTER(ckks_cache_desc_t), C.c_uint32, C.POINTER(C.c_uint32),
+                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_void_p)]),
     "ckks_encrypt_cached": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64),
                                       C.c_uint64, C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_add": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.POINTER(ckks_ct_batch_t),
@@ -124,6 +127,7 @@ _SIGS = {
                                    C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_decrypt_pixels": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.c_void_p, C.c_void_p]),
     "ckks_stream_sync": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ckks_stream_status": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ckks_image_pipeline": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
                                       C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(ckks_pipeline_config_t),
                                       C.c_void_p, C.c_void_p]),
@@ -131,7 +135,8 @@ _SIGS = {
     "ckks_batch_plan_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(ckks_batch_config_t),
                                          C.POINTER(C.c_void_p)]),
     "ckks_batch_run": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_double),
-                                 C.c_uint32, C.POINTER(C.c_uint64), C.c_uint64, C.c_void_p, C.c_void_p]),
+                                 C.c_uint32, C.POINTER(C.c_uint64), C.c_uint64, C.c_void_p,
+                                 C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_batch_plan_destroy": (None, [C.c_void_p]),
     "ckks_server_create": (C.c_int, [C.c_void_p, C.POINTER(ckks_server_config_t), C.POINTER(C.c_void_p)]),
     "ckks_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64),
@@ -241,6 +246,14 @@ class Ciphertexts:
     def batch(self) -> ckks_ct_batch_t:
         return ckks_ct_batch_t(self.data.data_ptr() if self.count else None, self.count, self.level, 0, self.scale)
 
+    def out_batch(self) -> ckks_ct_batch_t:
+        """Descriptor of this tensor as an output buffer: its real capacity (rows of the
+        tensor's own level), which the library checks against the result's size."""
+        d = self.data
+        if d.dim() != 4 or not d.is_contiguous():
+            raise ValueError("an output tensor must be a contiguous [count][2][level][N] tensor")
+        return ckks_ct_batch_t(d.data_ptr() if d.shape[0] else None, int(d.shape[0]), int(d.shape[2]), 0, self.scale)
+
     def to_numpy(self) -> np.ndarray:
         return self.data.cpu().numpy().view(np.uint64)
 
@@ -340,11 +353,28 @@ class Context:
                        stream=None) -> Ciphertexts:
         n = int(px.numel())
         out = self.empty(n) if out is None else out
-        b = out.batch()
+        b = out.out_batch()
         _check(lib().ckks_encrypt_pixels(self.handle, _ptr(px), n, _seed(seed), first_index, C.byref(b),
                                          _stream(stream)))
         out.level, out.scale = int(b.level), float(b.scale)
         return out
+
+    def cache_import(self, kind: int, values, entries, pool=None, base: int = 0, digits: int = 0, topk: int = 0,
+                     zero_pool: int = 0) -> "Cache":
+        """Install a cache from host arrays laid out as Cache.export returns them."""
+        vals = np.ascontiguousarray(values, dtype=np.uint32)
+        ent = np.ascontiguousarray(entries, dtype=np.uint64).reshape(-1)
+        pl = None if pool is None else np.ascontiguousarray(pool, dtype=np.uint64).reshape(-1)
+        if ent.size != vals.size * 2 * self.L * self.N:
+            raise ValueError("entries must hold len(values) ciphertexts of level L")
+        if pl is not None and pl.size != zero_pool * 2 * self.L * self.N:
+            raise ValueError("pool must hold zero_pool ciphertexts of level L")
+        desc = ckks_cache_desc_t(kind, base, digits, topk, zero_pool)
+        h = C.c_void_p()
+        _check(lib().ckks_cache_import(self.handle, C.byref(desc), vals.size, vals.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                       ent.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                       None if pl is None else pl.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(h)))
+        return Cache(h, self, kind)
 
     def cache_build(self, kind: int, base: int = 0, digits: int = 0, topk: int = 0, zero_pool: int = 0,
                     scan_px=None, seed=(0, 0), stream=None) -> "Cache":
@@ -359,7 +389,7 @@ class Context:
                        stream=None) -> Ciphertexts:
         n = int(px.numel())
         out = self.empty(n) if out is None else out
-        b = out.batch()
+        b = out.out_batch()
         _check(lib().ckks_encrypt_cached(self.handle, cache.handle, _ptr(px), n, _seed(seed), first_index,
                                          C.byref(b), _stream(stream)))
         out.level, out.scale = int(b.level), float(b.scale)
@@ -368,7 +398,7 @@ class Context:
     # -- homomorphic operations ---------------------------------------------------
     def _binary(self, fn, a: Ciphertexts, b: Ciphertexts, out, stream):
         out = self.empty(a.count, a.level) if out is None else out
-        ba, bb, bo = a.batch(), b.batch(), out.batch()
+        ba, bb, bo = a.batch(), b.batch(), out.out_batch()
         _check(fn(self.handle, C.byref(ba), C.byref(bb), C.byref(bo), _stream(stream)))
         out.level, out.scale = int(bo.level), float(bo.scale)
         return out
@@ -384,7 +414,7 @@ class Context:
 
     def mul_const(self, a: Ciphertexts, c: float, out=None, stream=None) -> Ciphertexts:
         out = self.empty(a.count, a.level) if out is None else out
-        ba, bo = a.batch(), out.batch()
+        ba, bo = a.batch(), out.out_batch()
         _check(lib().ckks_mul_const(self.handle, C.byref(ba), float(c), C.byref(bo), _stream(stream)))
         out.level, out.scale = int(bo.level), float(bo.scale)
         return out
@@ -396,14 +426,14 @@ class Context:
 
     def rescale(self, a: Ciphertexts, out=None, stream=None) -> Ciphertexts:
         out = self.empty(a.count, a.level - 1) if out is None else out
-        ba, bo = a.batch(), out.batch()
+        ba, bo = a.batch(), out.out_batch()
         _check(lib().ckks_rescale(self.handle, C.byref(ba), C.byref(bo), _stream(stream)))
         out.level, out.scale = int(bo.level), float(bo.scale)
         return out
 
     def mean_filter(self, img: Ciphertexts, H: int, W: int, k: int, out=None, stream=None) -> Ciphertexts:
         out = self.empty(img.count, img.level - 1) if out is None else out
-        bi, bo = img.batch(), out.batch()
+        bi, bo = img.batch(), out.out_batch()
         _check(lib().ckks_mean_filter(self.handle, C.byref(bi), H, W, k, C.byref(bo), _stream(stream)))
         out.level, out.scale = int(bo.level), float(bo.scale)
         return out
@@ -418,6 +448,14 @@ class Context:
 
     def stream_sync(self, stream=None):
         _check(lib().ckks_stream_sync(self.handle, _stream(stream)))
+
+    def stream_done(self, stream=None) -> bool:
+        """Non-blocking: True when the stream's work has completed (ckks_stream_status)."""
+        rc = lib().ckks_stream_status(self.handle, _stream(stream))
+        if rc == CKKS_PENDING:
+            return False
+        _check(rc)
+        return True
 
     def image_pipeline(self, px, H: int, W: int, seed, k: int, tile_rows: int, streams: int = 3,
                        cache: "Cache | None" = None, first_index: int = 0, out=None, stream=None):
@@ -493,7 +531,10 @@ class BatchPlan:
         self.ctx = ctx
         self.cache = cache
 
-    def run(self, px, seg_end, seg_b, seed, first_index: int = 0, out=None, stream=None):
+    def run(self, px, seg_end, seg_b, seed, first_index: int = 0, out=None, stream=None,
+            cts_out: "Ciphertexts | None" = None):
+        """Decrypted pixel + brightness values; with cts_out (n ciphertexts of level L) every
+        brightened ciphertext is also kept there."""
         import torch
 
         n = px.numel()
@@ -501,9 +542,12 @@ class BatchPlan:
             out = torch.empty(n, dtype=torch.float64, device=px.device)
         se = np.ascontiguousarray(seg_end, dtype=np.uint64)
         sb = np.ascontiguousarray(seg_b, dtype=np.float64)
+        cb = cts_out.out_batch() if cts_out is not None else None
         _check(lib().ckks_batch_run(self.handle, _ptr(px), n, se.ctypes.data_as(C.POINTER(C.c_uint64)),
                                     sb.ctypes.data_as(C.POINTER(C.c_double)), len(se), _seed(seed), int(first_index),
-                                    _ptr(out), _stream(stream)))
+                                    _ptr(out), C.byref(cb) if cb is not None else None, _stream(stream)))
+        if cts_out is not None:
+            cts_out.level, cts_out.scale = int(cb.level), float(cb.scale)
         return out
 
     def close(self):

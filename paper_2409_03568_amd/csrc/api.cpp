@@ -105,6 +105,30 @@ int check_batch(const ckks_ctx *c, const ckks_ct_batch *b, const char *name) {
   return CKKS_OK;
 }
 
+// An output descriptor's incoming count and level describe its buffer: count = 0 means
+// the caller vouches for the size; otherwise the buffer holds count ciphertexts of level
+// `level` (0: the result's level), and must have room for n ciphertexts at result_level.
+int check_out(const ckks_ctx *c, const ckks_ct_batch *out, uint64_t n, uint32_t result_level) {
+  if (!out) return fail(CKKS_EINVAL, "out is NULL");
+  if (n && !out->data) return fail(CKKS_EINVAL, "out data is NULL");
+  if (!out->count) return CKKS_OK;
+  const uint32_t lv = out->level ? out->level : result_level;
+  if (lv < 1 || lv > (uint32_t)c->prm.L) return fail(CKKS_ELEVEL, "out: level %u outside [1, %d]", lv, c->prm.L);
+  const unsigned __int128 have = (unsigned __int128)out->count * ct_words(c, lv);
+  const unsigned __int128 need = (unsigned __int128)n * ct_words(c, result_level);
+  if (have < need)
+    return fail(CKKS_EINVAL, "out holds %llu ciphertexts of level %u, the result needs %llu of level %u",
+                (unsigned long long)out->count, lv, (unsigned long long)n, result_level);
+  return CKKS_OK;
+}
+
+int check_cache(const ckks_ctx *c, const ckks_cache *cache) {
+  if (!cache || cache->ctx != c) return fail(CKKS_ECACHE, "cache is NULL or belongs to another context");
+  if (cache->key_epoch != c->key_epoch)
+    return fail(CKKS_ESTATE, "the cache was built under keys that have since been replaced");
+  return CKKS_OK;
+}
+
 // Constant c as a per-limb multiplier (integer c keeps the scale unless `scaled`; any
 // other c becomes K = rint(c * q_{level-1}) at scale * q_{level-1}).
 int const_multiplier(const ckks_ctx *c, uint32_t level, double scale, double cst, std::vector<uint64_t> &K,
@@ -171,6 +195,25 @@ hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const
 int filter_multiplier(const ckks_ctx *c, uint32_t level, double scale, uint32_t k, std::vector<uint64_t> &K,
                       double *new_scale) {
   return const_multiplier(c, level, scale, 1.0 / (double)(k * k), K, new_scale, true);
+}
+
+double encryption_terms(const ckks_cache *cache) {
+  if (!cache) return 1.0;
+  if (cache->kind != CKKS_CACHE_RADIX) return 2.0;  // entry + pool member
+  // radix: Enc(0) plus k_i Enc(r^i) with |k_i| = |d_i + b_i - r b_{i+1}| <= 2r
+  return 1.0 + 2.0 * cache->base * cache->digits;
+}
+
+bool limb0_decode_exact(const ckks_ctx *c, double value_bound, double terms, bool filtered) {
+  const double N = (double)c->N, B = (double)c->prm.B;
+  // message: |rint(p T_j)| <= |p| Delta 2^(1 - log N) + 1/2 for each encoded term
+  double x = value_bound * ldexp(c->scale, 1 - c->prm.log_n) + 2.0;
+  // noise of one encryption: v e + e0 + e1 s with v, s ternary and |e| <= B in every coefficient
+  x += terms * (2.0 * N + 1.0) * B;
+  // a filter output is (K sum)/q_last plus the rescale rounding r0 + r1 s over q_last, with
+  // K <= q_last / k^2 + 1/2: at most the input bound (1 + k^2 / (2 q_last)) plus (N + 1) / 2
+  if (filtered) x = x * (1.0 + 1.0 / 1048576.0) + N;
+  return x < 0.49 * (double)c->prm.q[0];
 }
 
 int api_fail(int code, const char *fmt, ...) {
@@ -261,6 +304,7 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
       lc.pmod[i] = host::centered(r.qP % q, q);
     }
   }
+  if (L >= 2) lc.q0inv_q1 = host::centered(host::inv_mod(r.q[0] % r.q[1], r.q[1]), r.q[1]);
   // the transforms' lazy-reduction schedule is compiled per class of prime sizes
   c->rc = qmax < 1099511627776.0 ? 0 : 1;
   // values per NTT thread (measured on MI355X at N = 8192): encryption, decryption and
@@ -364,6 +408,11 @@ int ckks_keygen(ckks_ctx *ctx, const uint64_t seed[2]) {
   if (rc) return rc;
   if (!seed) return fail(CKKS_EINVAL, "seed is NULL");
   DeviceGuard g(ctx->device);
+  // the old keys are gone from here on: key-switching keys of the old s and every cache,
+  // plan or server built under them become invalid
+  ctx->has_keys = false;
+  ctx->has_relin = false;
+  ctx->key_epoch++;
   HIP_TRY(launch_keygen(ctx, seed[0], seed[1], nullptr), "keygen launch");
   HIP_TRY(launch_keys_prepare(ctx, nullptr), "key preparation launch");
   HIP_TRY(hipDeviceSynchronize(), "keygen");
@@ -424,6 +473,9 @@ int ckks_keys_import(ckks_ctx *ctx, const int64_t *host_s, const uint64_t *host_
       for (size_t j = 0; j < N; j++)
         if (host_pk[(p * L + i) * N + j] >= ctx->prm.q[i]) return fail(CKKS_EINVAL, "public key residue not canonical");
   DeviceGuard g(ctx->device);
+  ctx->has_keys = false;
+  ctx->has_relin = false;
+  ctx->key_epoch++;
   HIP_TRY(hipMemcpy(ctx->dev.s, host_s, N * sizeof(int64_t), hipMemcpyHostToDevice), "import s");
   HIP_TRY(hipMemcpy(ctx->dev.pk, host_pk, 2 * L * N * sizeof(uint64_t), hipMemcpyHostToDevice), "import pk");
   HIP_TRY(launch_keys_prepare(ctx, nullptr), "key preparation launch");
@@ -437,8 +489,9 @@ int ckks_encrypt_pixels(ckks_ctx *ctx, const uint8_t *d_px, uint64_t n, const ui
   int rc = check_keys(ctx);
   if (rc) return rc;
   if (!seed || !out) return fail(CKKS_EINVAL, "seed/out is NULL");
-  if (n && (!d_px || !out->data)) return fail(CKKS_EINVAL, "pixel or output pointer is NULL");
+  if (n && !d_px) return fail(CKKS_EINVAL, "pixel pointer is NULL");
   if (n > 0xFFFFFFFFull) return fail(CKKS_EINVAL, "at most 2^32-1 pixels per call");
+  if ((rc = check_out(ctx, out, n, (uint32_t)ctx->prm.L))) return rc;
   out->count = n;
   out->level = (uint32_t)ctx->prm.L;
   out->scale = ctx->scale;
@@ -469,7 +522,9 @@ int ckks_cache_build(ckks_ctx *ctx, const ckks_cache_desc *desc, const uint8_t *
   std::vector<int16_t> slot_of(256, -1);
   if (kind == CKKS_CACHE_RADIX) {
     const uint32_t r = desc->base, D = desc->digits;
-    if (r < 2 || r > 256 || D < 1 || D > (uint32_t)kMaxDigits) return fail(CKKS_ECACHE, "radix base must be in [2,256], digits in [1,8]");
+    // one digit would leave no radix randomness (Sec. 3.3 draws one bit per radix above the
+    // lowest), so every pixel value would map to one fixed ciphertext
+    if (r < 2 || r > 256 || D < 2 || D > (uint32_t)kMaxDigits) return fail(CKKS_ECACHE, "radix base must be in [2,256], digits in [2,8]");
     uint64_t pw = 1;
     for (uint32_t i = 0; i + 1 < D; i++) pw *= r;
     if (pw > 255) return fail(CKKS_ECACHE, "base^(digits-1) = %llu exceeds 255", (unsigned long long)pw);
@@ -507,6 +562,7 @@ int ckks_cache_build(ckks_ctx *ctx, const ckks_cache_desc *desc, const uint8_t *
   hipStream_t st = as_stream(stream);
   ckks_cache *c = new ckks_cache();
   c->ctx = ctx;
+  c->key_epoch = ctx->key_epoch;
   c->device = ctx->device;
   c->kind = kind;
   c->base = desc->base;
@@ -619,14 +675,104 @@ int ckks_cache_export(ckks_cache *cache, uint32_t *host_values, uint64_t *host_e
   return CKKS_OK;
 }
 
+int ckks_cache_import(ckks_ctx *ctx, const ckks_cache_desc *desc, uint32_t n_entries, const uint32_t *host_values,
+                      const uint64_t *host_entries, const uint64_t *host_pool, ckks_cache **out) {
+  int rc = check_keys(ctx);
+  if (rc) return rc;
+  if (!desc || !out || !host_values || !host_entries) return fail(CKKS_EINVAL, "desc/out/values/entries is NULL");
+  *out = nullptr;
+  const int kind = desc->kind;
+  const uint32_t n = n_entries;
+  std::vector<int16_t> slot_of(256, -1);
+  if (kind == CKKS_CACHE_RADIX) {
+    const uint32_t r = desc->base, D = desc->digits;
+    if (r < 2 || r > 256 || D < 2 || D > (uint32_t)kMaxDigits) return fail(CKKS_ECACHE, "radix base must be in [2,256], digits in [2,8]");
+    uint64_t top = 1;
+    for (uint32_t i = 0; i + 1 < D; i++) top *= r;
+    if (top > 255 || top * r < 256) return fail(CKKS_ECACHE, "base^(digits-1) must be <= 255 and base^digits >= 256");
+    if (n != D + 1) return fail(CKKS_ECACHE, "a radix cache has digits + 1 = %u entries, got %u", D + 1, n);
+    uint64_t pw = 1;
+    for (uint32_t i = 0; i < n; i++) {
+      const uint64_t want = i == 0 ? 0 : pw;
+      if (host_values[i] != want) return fail(CKKS_ECACHE, "radix entry %u must encrypt %llu", i, (unsigned long long)want);
+      if (i) pw *= r;
+    }
+  } else if (kind == CKKS_CACHE_VALUE_TOPK || kind == CKKS_CACHE_VALUE_FULL) {
+    if (desc->zero_pool < 1 || desc->zero_pool > 4096) return fail(CKKS_ECACHE, "zero_pool must be in [1, 4096]");
+    if (!host_pool) return fail(CKKS_EINVAL, "a value cache needs its pool of encrypted zeros");
+    if (kind == CKKS_CACHE_VALUE_FULL && n != 256) return fail(CKKS_ECACHE, "a full cache has 256 entries, got %u", n);
+    if (kind == CKKS_CACHE_VALUE_TOPK && (desc->topk < 1 || desc->topk > 256 || n < 1 || n > desc->topk))
+      return fail(CKKS_ECACHE, "a top-k cache has 1..topk entries (topk <= 256), got %u", n);
+    for (uint32_t i = 0; i < n; i++) {
+      const uint32_t v = host_values[i];
+      if (v > 255 || slot_of[v] >= 0) return fail(CKKS_ECACHE, "entry values must be distinct pixel values (entry %u)", i);
+      if (kind == CKKS_CACHE_VALUE_FULL && v != i) return fail(CKKS_ECACHE, "full-cache entry %u must encrypt %u", i, i);
+      slot_of[v] = (int16_t)i;
+    }
+  } else {
+    return fail(CKKS_ECACHE, "unknown cache kind %d", kind);
+  }
+  const uint32_t npool = kind == CKKS_CACHE_RADIX ? 0 : desc->zero_pool;
+  const size_t N = (size_t)ctx->N, L = (size_t)ctx->prm.L, S = 2 * L * N;
+  auto canonical = [&](const uint64_t *ct) {
+    for (size_t p = 0; p < 2; p++)
+      for (size_t i = 0; i < L; i++)
+        for (size_t j = 0; j < N; j++)
+          if (ct[(p * L + i) * N + j] >= ctx->prm.q[i]) return false;
+    return true;
+  };
+  for (uint32_t i = 0; i < n; i++)
+    if (!canonical(host_entries + (size_t)i * S)) return fail(CKKS_EINVAL, "entry %u has a residue that is not canonical", i);
+  for (uint32_t u = 0; u < npool; u++)
+    if (!canonical(host_pool + (size_t)u * S)) return fail(CKKS_EINVAL, "pool member %u has a residue that is not canonical", u);
+  DeviceGuard g(ctx->device);
+  ckks_cache *c = new ckks_cache();
+  c->ctx = ctx;
+  c->key_epoch = ctx->key_epoch;
+  c->device = ctx->device;
+  c->kind = kind;
+  c->base = desc->base;
+  c->digits = desc->digits;
+  c->topk = desc->topk;
+  c->pool = npool;
+  c->n_slots = n;
+  std::vector<uint32_t> vals(host_values, host_values + n);
+  std::vector<uint64_t> ts(n);
+  for (uint32_t i = 0; i < n; i++) ts[i] = kind == CKKS_CACHE_RADIX ? i : 256 + (uint64_t)vals[i];
+  hipError_t e = dev_alloc(&c->entries, (size_t)n * S);
+  if (e == hipSuccess && npool) e = dev_alloc(&c->pool_cts, (size_t)npool * S);
+  if (e == hipSuccess) e = dev_alloc(&c->slot_of, 256);
+  if (e == hipSuccess) e = dev_alloc(&c->vals, n);
+  if (e == hipSuccess) e = dev_alloc(&c->ts, n);
+  if (e == hipSuccess) e = dev_alloc(&c->count, 1);
+  if (e != hipSuccess) {
+    ckks_cache_destroy(c);
+    return fail(CKKS_ENOMEM, "cache allocation failed: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(c->entries, host_entries, (size_t)n * S * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && npool)
+    e = hipMemcpy(c->pool_cts, host_pool, (size_t)npool * S * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = upload(c->slot_of, slot_of);
+  if (e == hipSuccess) e = upload(c->vals, vals);
+  if (e == hipSuccess) e = upload(c->ts, ts);
+  if (e == hipSuccess) e = hipMemcpy(c->count, &n, sizeof(n), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    ckks_cache_destroy(c);
+    return hip_fail(e, "cache upload");
+  }
+  *out = c;
+  return CKKS_OK;
+}
+
 int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
                         const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream) {
   int rc = check_keys(ctx);
   if (rc) return rc;
-  if (!cache || cache->ctx != ctx) return fail(CKKS_ECACHE, "cache is NULL or belongs to another context");
+  if ((rc = check_cache(ctx, cache))) return rc;
   if (!seed || !out) return fail(CKKS_EINVAL, "seed/out is NULL");
-  if (n && (!d_px || !out->data)) return fail(CKKS_EINVAL, "pixel or output pointer is NULL");
+  if (n && !d_px) return fail(CKKS_EINVAL, "pixel pointer is NULL");
   if (n > 0xFFFFFFFFull) return fail(CKKS_EINVAL, "at most 2^32-1 pixels per call");
+  if ((rc = check_out(ctx, out, n, (uint32_t)ctx->prm.L))) return rc;
   out->count = n;
   out->level = (uint32_t)ctx->prm.L;
   out->scale = ctx->scale;
@@ -652,8 +798,7 @@ static int binary_common(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_ba
   if (a->count != b->count) return fail(CKKS_EINVAL, "counts differ (%llu vs %llu)", (unsigned long long)a->count, (unsigned long long)b->count);
   if (a->level != b->level) return fail(CKKS_ELEVEL, "levels differ (%u vs %u)", a->level, b->level);
   if (a->scale != b->scale) return fail(CKKS_ESCALE, "scales differ (%.17g vs %.17g)", a->scale, b->scale);
-  if (a->count && !out->data) return fail(CKKS_EINVAL, "out data is NULL");
-  return CKKS_OK;
+  return check_out(ctx, out, a->count, a->level);
 }
 
 int ckks_add(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream) {
@@ -692,7 +837,7 @@ int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
   if (a->level != b->level) return fail(CKKS_ELEVEL, "levels differ (%u vs %u)", a->level, b->level);
   const double ns = a->scale * b->scale;
   if (!isfinite(ns)) return fail(CKKS_ESCALE, "product scale overflows");
-  if (a->count && !out->data) return fail(CKKS_EINVAL, "out data is NULL");
+  if ((rc = check_out(ctx, out, a->count, a->level))) return rc;
   const uint64_t words = a->count * ct_words(ctx, a->level);
   for (const ckks_ct_batch *in : {a, b})
     if (a->count && in->data != out->data && overlaps(in->data, words, out->data, words))
@@ -717,7 +862,7 @@ int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
 int ckks_mul_const(ckks_ctx *ctx, const ckks_ct_batch *a, double c, ckks_ct_batch *out, void *stream) {
   int rc = check_ctx(ctx);
   if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
-  if (!out || (a->count && !out->data)) return fail(CKKS_EINVAL, "out is NULL");
+  if ((rc = check_out(ctx, out, a->count, a->level))) return rc;
   std::vector<uint64_t> K;
   double ns = 0;
   if ((rc = const_multiplier(ctx, a->level, a->scale, c, K, &ns))) return rc;
@@ -745,7 +890,7 @@ int ckks_rescale(ckks_ctx *ctx, const ckks_ct_batch *a, ckks_ct_batch *out, void
   int rc = check_ctx(ctx);
   if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
   if (a->level < 2) return fail(CKKS_ELEVEL, "rescale needs level >= 2");
-  if (!out || (a->count && !out->data)) return fail(CKKS_EINVAL, "out is NULL");
+  if ((rc = check_out(ctx, out, a->count, a->level - 1))) return rc;
   const uint64_t nin = a->count * ct_words(ctx, a->level), nout = a->count * ct_words(ctx, a->level - 1);
   if (a->count && overlaps(a->data, nin, out->data, nout)) return fail(CKKS_EINVAL, "rescale output overlaps its input");
   const ckks_ct_batch av = *a;
@@ -765,7 +910,7 @@ int ckks_mean_filter(ckks_ctx *ctx, const ckks_ct_batch *img, uint32_t H, uint32
   if (k != 1 && k != 3 && k != 5 && k != 7) return fail(CKKS_EUNSUPPORTED, "window k must be 1, 3, 5 or 7");
   if (img->level < 2 || img->level > 8) return fail(CKKS_ELEVEL, "mean filter needs 2 <= level <= 8");
   if ((uint64_t)H * W != img->count) return fail(CKKS_EINVAL, "H*W (%llu) != count (%llu)", (unsigned long long)H * W, (unsigned long long)img->count);
-  if (!out || (img->count && !out->data)) return fail(CKKS_EINVAL, "out is NULL");
+  if ((rc = check_out(ctx, out, img->count, img->level - 1))) return rc;
   const uint64_t nin = img->count * ct_words(ctx, img->level), nout = img->count * ct_words(ctx, img->level - 1);
   if (img->count && overlaps(img->data, nin, out->data, nout)) return fail(CKKS_EINVAL, "filter output overlaps its input");
   std::vector<uint64_t> K;
@@ -789,7 +934,9 @@ int ckks_decrypt_pixels(ckks_ctx *ctx, const ckks_ct_batch *in, double *d_out, v
   if (in->count && !d_out) return fail(CKKS_EINVAL, "d_out is NULL");
   if (!in->count) return CKKS_OK;
   DeviceGuard g(ctx->device);
-  HIP_TRY(launch_decrypt(ctx, in->data, in->count, (int)in->level, in->scale, d_out, as_stream(stream)), "decrypt");
+  HIP_TRY(launch_decrypt(ctx, in->data, in->count, (int)in->level, in->scale, d_out, in->level >= 2 ? 2 : 1,
+                         as_stream(stream)),
+          "decrypt");
   return CKKS_OK;
 }
 
@@ -798,6 +945,17 @@ int ckks_stream_sync(ckks_ctx *ctx, void *stream) {
   if (rc) return rc;
   DeviceGuard g(ctx->device);
   HIP_TRY(hipStreamSynchronize(as_stream(stream)), "stream synchronize");
+  HIP_TRY(hipGetLastError(), "earlier launch");
+  return CKKS_OK;
+}
+
+int ckks_stream_status(ckks_ctx *ctx, void *stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  const hipError_t q = hipStreamQuery(as_stream(stream));
+  if (q == hipErrorNotReady) return CKKS_PENDING;
+  HIP_TRY(q, "stream query");
   HIP_TRY(hipGetLastError(), "earlier launch");
   return CKKS_OK;
 }

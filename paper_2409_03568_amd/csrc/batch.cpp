@@ -37,9 +37,12 @@ struct RunKey {
   uint64_t seed[2] = {0, 0};
   uint64_t first_index = 0;
   double *out = nullptr;
+  uint64_t *cts = nullptr;  // caller's ciphertext buffer, or NULL for the ring
+  int dec_limbs = 1;
   bool operator==(const RunKey &o) const {
     return px == o.px && n == o.n && seg_end == o.seg_end && seg_b == o.seg_b && seed[0] == o.seed[0] &&
-           seed[1] == o.seed[1] && first_index == o.first_index && out == o.out;
+           seed[1] == o.seed[1] && first_index == o.first_index && out == o.out && cts == o.cts &&
+           dec_limbs == o.dec_limbs;
   }
 };
 
@@ -47,6 +50,7 @@ struct RunKey {
 
 struct ckks_batch_plan {
   ckks_ctx *ctx = nullptr;
+  uint64_t key_epoch = 0;        // keys the plan was made under
   const ckks_cache *cache = nullptr;
   ckks_batch_config cfg{};
   uint64_t *ring = nullptr;      // [chunk][2][L][N]
@@ -87,15 +91,17 @@ void free_plan(ckks_batch_plan *p) {
 hipError_t enqueue_chunks(ckks_batch_plan *p, const RunKey &k, uint32_t n_seg, hipStream_t st) {
   const ckks_ctx *c = p->ctx;
   const uint64_t chunk = p->cfg.chunk_cts;
+  const uint64_t S = 2 * (uint64_t)c->prm.L * (uint64_t)c->N;
   for (uint64_t first = 0; first < k.n; first += chunk) {
     const uint64_t cnt = k.n - first < chunk ? k.n - first : chunk;
+    uint64_t *ring = k.cts ? k.cts + first * S : p->ring;
     EncJob job;
     job.px = k.px + first;
     job.n = cnt;
     job.first_index = k.first_index + first;
     job.seed0 = k.seed[0];
     job.seed1 = k.seed[1];
-    job.out = p->ring;
+    job.out = ring;
     job.seg_end = p->seg_end;
     job.seg_b = p->seg_b;
     job.n_seg = n_seg;
@@ -105,14 +111,14 @@ hipError_t enqueue_chunks(ckks_batch_plan *p, const RunKey &k, uint32_t n_seg, h
     if (p->cache) {
       e = launch_value_meta(c, p->cache, job.px, cnt, job.first_index, job.seed0, job.seed1, p->meta, p->miss,
                             p->counters, p->hits, st);
-      if (e == hipSuccess) e = launch_value_gather(c, p->cache, p->meta, p->counters, p->hits, cnt, p->ring, &job, st);
+      if (e == hipSuccess) e = launch_value_gather(c, p->cache, p->meta, p->counters, p->hits, cnt, ring, &job, st);
       job.list = p->miss;
       job.list_count = p->counters;
       if (e == hipSuccess) e = launch_encrypt(c, job, cnt < kListGrid ? cnt : kListGrid, st);
     } else {
       e = launch_encrypt(c, job, cnt < (1u << 24) ? cnt : (1u << 24), st);
     }
-    if (e == hipSuccess) e = launch_decrypt(c, p->ring, cnt, c->prm.L, c->scale, k.out + first, st);
+    if (e == hipSuccess) e = launch_decrypt(c, ring, cnt, c->prm.L, c->scale, k.out + first, k.dec_limbs, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -129,10 +135,13 @@ int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_ba
   if (!ctx->has_keys) return api_fail(CKKS_ESTATE, "no keys on the context");
   if (cfg->chunk_cts < 1 || cfg->chunk_cts > 0xFFFFFFFFull) return api_fail(CKKS_EINVAL, "chunk_cts must be 1..2^32-1");
   if (cache && cache->ctx != ctx) return api_fail(CKKS_ECACHE, "cache belongs to another context");
+  if (cache && cache->key_epoch != ctx->key_epoch)
+    return api_fail(CKKS_ESTATE, "the cache was built under keys that have since been replaced");
   if (cache && cache->kind == CKKS_CACHE_RADIX) return api_fail(CKKS_EUNSUPPORTED, "batches take a value cache or none");
   DeviceScope g(ctx->device);
   ckks_batch_plan *p = new ckks_batch_plan;
   p->ctx = ctx;
+  p->key_epoch = ctx->key_epoch;
   p->cache = cache;
   p->cfg = *cfg;
   const uint64_t chunk = cfg->chunk_cts;
@@ -153,19 +162,36 @@ int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_ba
 
 int ckks_batch_run(ckks_batch_plan *p, const uint8_t *d_px, uint64_t n, const uint64_t *host_seg_end,
                    const double *host_seg_b, uint32_t n_seg, const uint64_t seed[2], uint64_t first_index,
-                   double *d_out, void *stream) {
+                   double *d_out, ckks_ct_batch *cts_out, void *stream) {
   if (!p || !seed) return api_fail(CKKS_EINVAL, "plan/seed is NULL");
+  ckks_ctx *c = p->ctx;
+  if (p->key_epoch != c->key_epoch) return api_fail(CKKS_ESTATE, "the keys were replaced after the plan was made");
+  const uint32_t L = (uint32_t)c->prm.L;
+  if (cts_out) {
+    if (n && !cts_out->data) return api_fail(CKKS_EINVAL, "cts_out data is NULL");
+    if (cts_out->count && (cts_out->level ? cts_out->level : L) != L)
+      return api_fail(CKKS_ELEVEL, "cts_out must hold ciphertexts of level %u", L);
+    if (cts_out->count && cts_out->count < n)
+      return api_fail(CKKS_EINVAL, "cts_out holds %llu ciphertexts, the batch has %llu",
+                      (unsigned long long)cts_out->count, (unsigned long long)n);
+  }
   if (n == 0) return CKKS_OK;
   if (!d_px || !d_out || !host_seg_end || !host_seg_b) return api_fail(CKKS_EINVAL, "NULL buffer");
   if (n_seg < 1) return api_fail(CKKS_EINVAL, "need at least one image");
-  ckks_ctx *c = p->ctx;
   const double bscale = ldexp(c->scale, 1 - c->prm.log_n);
+  double bmax = 0.0;
   for (uint32_t i = 0; i < n_seg; i++) {
     if (i && host_seg_end[i] < host_seg_end[i - 1]) return api_fail(CKKS_EINVAL, "seg_end must be ascending");
     if (!(fabs(host_seg_b[i] * bscale) < 1125899906842624.0))  // 2^50
       return api_fail(CKKS_EINVAL, "brightness %g too large for the fused encoding", host_seg_b[i]);
+    bmax = fmax(bmax, fabs(host_seg_b[i]));
   }
   if (host_seg_end[n_seg - 1] != n) return api_fail(CKKS_EINVAL, "last seg_end must equal n");
+  if (cts_out) {
+    cts_out->count = n;
+    cts_out->level = L;
+    cts_out->scale = c->scale;
+  }
   DeviceScope g(c->device);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   RunKey k;
@@ -177,6 +203,10 @@ int ckks_batch_run(ckks_batch_plan *p, const uint8_t *d_px, uint64_t n, const ui
   k.seed[1] = seed[1];
   k.first_index = first_index;
   k.out = d_out;
+  k.cts = cts_out ? cts_out->data : nullptr;
+  // pixels plus brightness, one or two fresh error terms: limb 0 decodes exactly unless the
+  // parameters leave no room (then the two-limb lift)
+  k.dec_limbs = limb0_decode_exact(c, 255.0 + bmax, encryption_terms(p->cache), false) || L < 2 ? 1 : 2;
   const bool same = p->have_key && p->key == k;
   if (!same) {
     // the segment tables may still be read by work enqueued for an earlier run: let it
@@ -272,7 +302,7 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e == hipSuccess && rep) enc_ms[w] = fmin(enc_ms[w], ms);
       if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-      if (e == hipSuccess) e = launch_decrypt(ctx, cts, trial_cts, (int)L, ctx->scale, dec, nullptr);
+      if (e == hipSuccess) e = launch_decrypt(ctx, cts, trial_cts, (int)L, ctx->scale, dec, 1, nullptr);
       if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

@@ -27,6 +27,7 @@ struct LimbConsts {
   uint64_t qi[kMaxL + 1];
   double pinv[kMaxL];        // qP^-1 mod q_i, centered (ModDown)
   double pmod[kMaxL];        // qP mod q_i, centered (the s^2 term of key-switching key i)
+  double q0inv_q1;           // q_0^-1 mod q_1, centered (two-limb CRT of decryption)
 };
 
 // Device tables owned by a context.
@@ -99,6 +100,9 @@ struct ckks_ctx {
   std::vector<uint64_t> ninv;  // N^-1 mod q_i
   bool has_keys = false;
   bool has_relin = false;      // key-switching keys of s^2 generated
+  // Incremented whenever the keys are replaced (keygen, import): caches, batch plans and
+  // servers remember the epoch they were made under and refuse to run after a change.
+  uint64_t key_epoch = 0;
   hipStream_t pipe[3] = {nullptr, nullptr, nullptr};  // image pipeline stages, created on first use
   hipMemPool_t pool = nullptr;  // stream-ordered scratch that keeps its memory between calls
 };
@@ -106,6 +110,7 @@ struct ckks_ctx {
 
 struct ckks_cache {
   ckks_ctx *ctx = nullptr;
+  uint64_t key_epoch = 0;         // keys the entries were encrypted under
   int device = 0;
   int kind = 0;
   uint32_t base = 0, digits = 0, topk = 0, pool = 0;
@@ -143,12 +148,24 @@ hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const
                              uint64_t seed0, uint64_t seed1, uint64_t first_index, uint64_t *out, void *ws,
                              hipStream_t stream);
 
+// Number of fresh-encryption error terms a ciphertext of this cache kind carries (1 for
+// plain encryption, cache == NULL).
+double encryption_terms(const ckks_cache *cache);
+// True when limb 0 alone decodes exactly every ciphertext that encrypts a slot-0 value of
+// magnitude at most value_bound at the context's scale with `terms` fresh error terms,
+// optionally after one k x k mean filter: a worst-case bound on the decrypted
+// coefficients (message, errors bounded by the Gaussian tail cut, rescale rounding) stays
+// below q_0/2.  Internal pipelines whose inputs are pixels use it to decode one limb.
+bool limb0_decode_exact(const ckks_ctx *c, double value_bound, double terms, bool filtered);
+
 // Launchers (return a hipError_t; enqueue on `stream`).
 hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
 hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream);
 hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream);
+// limbs = 1: decode the centered residue of limb 0; limbs = 2 (level >= 2): decode the
+// centered CRT lift of limbs 0 and 1.
 hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
-                          hipStream_t stream);
+                          int limbs, hipStream_t stream);
 // Key-switching keys of s^2 (grid: digits x primes), then their NTT-domain copies.
 hipError_t launch_relin_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
 hipError_t launch_relin_prepare(const ckks_ctx *c, hipStream_t stream);

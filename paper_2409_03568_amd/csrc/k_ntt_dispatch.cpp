@@ -7,7 +7,8 @@ namespace ckks {
   hipError_t launch_encrypt_##LOGN(const ckks_ctx *, const EncJob &, uint64_t, hipStream_t);                 \
   hipError_t launch_keygen_##LOGN(const ckks_ctx *, uint64_t, uint64_t, hipStream_t);                        \
   hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *, hipStream_t);                                      \
-  hipError_t launch_decrypt_##LOGN(const ckks_ctx *, const uint64_t *, uint64_t, int, double, double *, hipStream_t); \
+  hipError_t launch_decrypt_##LOGN(const ckks_ctx *, const uint64_t *, uint64_t, int, double, double *, int,   \
+                                   hipStream_t);                                                              \
   hipError_t launch_relin_keygen_##LOGN(const ckks_ctx *, uint64_t, uint64_t, hipStream_t);                  \
   hipError_t launch_relin_prepare_##LOGN(const ckks_ctx *, hipStream_t);                                     \
   hipError_t launch_mul_##LOGN(const ckks_ctx *, const uint64_t *, const uint64_t *, uint64_t *, uint64_t, int, \
@@ -34,8 +35,8 @@ hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipS
 }
 hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream) { CKKS_RING_SWITCH(launch_keys_prepare, stream) }
 hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
-                          hipStream_t stream) {
-  CKKS_RING_SWITCH(launch_decrypt, cts, n, level, scale, out, stream)
+                          int limbs, hipStream_t stream) {
+  CKKS_RING_SWITCH(launch_decrypt, cts, n, level, scale, out, limbs, stream)
 }
 hipError_t launch_relin_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream) {
   CKKS_RING_SWITCH(launch_relin_keygen, seed0, seed1, stream)

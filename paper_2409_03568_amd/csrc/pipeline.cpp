@@ -56,6 +56,8 @@ extern "C" int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const
   if (!ctx || !cfg || !seed) return api_fail(CKKS_EINVAL, "ctx/cfg/seed is NULL");
   if (!ctx->has_keys) return api_fail(CKKS_ESTATE, "no keys on the context");
   if (cache && cache->ctx != ctx) return api_fail(CKKS_ECACHE, "cache belongs to another context");
+  if (cache && cache->key_epoch != ctx->key_epoch)
+    return api_fail(CKKS_ESTATE, "the cache was built under keys that have since been replaced");
   const uint32_t k = cfg->filter_k;
   if (k != 1 && k != 3 && k != 5 && k != 7) return api_fail(CKKS_EUNSUPPORTED, "filter_k must be 1, 3, 5 or 7");
   const uint32_t L = (uint32_t)ctx->prm.L;
@@ -70,6 +72,8 @@ extern "C" int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const
   int rc = filter_multiplier(ctx, L, ctx->scale, k, K, &s1);
   if (rc) return rc;
   const double out_scale = s1 / (double)ctx->prm.q[L - 1];
+  // filtered pixels: limb 0 decodes exactly unless the parameters leave no room
+  const int dec_limbs = limb0_decode_exact(ctx, 255.0, encryption_terms(cache), true) || L < 3 ? 1 : 2;
   DeviceScope g(ctx->device);
   hipStream_t user = reinterpret_cast<hipStream_t>(stream);
   const uint32_t R = k / 2, T = cfg->tile_rows < H ? cfg->tile_rows : H;
@@ -136,7 +140,8 @@ extern "C" int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const
     if (e == hipSuccess && nbuf == 2) e = hipEventRecord(ev_flt(b), F);
     if (e == hipSuccess && nbuf == 2) e = hipStreamWaitEvent(D, ev_flt(b), 0);
     if (e == hipSuccess)
-      e = launch_decrypt(ctx, flt[b], (uint64_t)(r1 - r0) * W, (int)L - 1, out_scale, d_out + (uint64_t)r0 * W, D);
+      e = launch_decrypt(ctx, flt[b], (uint64_t)(r1 - r0) * W, (int)L - 1, out_scale, d_out + (uint64_t)r0 * W,
+                         dec_limbs, D);
     if (e == hipSuccess && nbuf == 2) e = hipEventRecord(ev_dec(b), D);
   }
   if (nbuf == 2) {

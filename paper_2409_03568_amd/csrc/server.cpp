@@ -57,6 +57,8 @@ struct Slot {
 
 struct ckks_server {
   ckks_ctx *ctx = nullptr;
+  uint64_t key_epoch = 0;  // keys the server was created under
+  int dec_limbs = 1;       // limbs decoded by decryption (see limb0_decode_exact)
   ckks_server_config cfg{};
   uint8_t *arena = nullptr;
   ckks::rt::Admission adm;
@@ -123,7 +125,10 @@ int launch_job(ckks_server *s, Slot &sl) {
   if (rc) return rc;
   ckks_ct_batch flt{d_flt, 0, 0, 0, 0.0};
   if (s->cfg.filter_k && (rc = ckks_mean_filter(ctx, &ct, j.H, j.W, s->cfg.filter_k, &flt, st))) return rc;
-  if ((rc = ckks_decrypt_pixels(ctx, s->cfg.filter_k ? &flt : &ct, d_out, st))) return rc;
+  const ckks_ct_batch &res = s->cfg.filter_k ? flt : ct;
+  if (ckks::launch_decrypt(ctx, res.data, res.count, (int)res.level, res.scale, d_out,
+                           res.level >= 2 ? s->dec_limbs : 1, sl.st) != hipSuccess)
+    return CKKS_EDEVICE;
   if (hipMemcpyAsync(sl.pin_out, d_out, j.n * sizeof(double), hipMemcpyDeviceToHost, sl.st) != hipSuccess)
     return CKKS_EDEVICE;
   return CKKS_OK;
@@ -226,9 +231,13 @@ int ckks_server_create(ckks_ctx *ctx, const ckks_server_config *cfg, ckks_server
   if (k != 0 && k != 1 && k != 3 && k != 5 && k != 7) return ckks::api_fail(CKKS_EUNSUPPORTED, "filter_k must be 0, 1, 3, 5 or 7");
   if (k && (ctx->prm.L < 2 || ctx->prm.L > 8)) return ckks::api_fail(CKKS_ELEVEL, "the mean filter needs 2..8 limbs");
   if (cfg->cache && cfg->cache->ctx != ctx) return ckks::api_fail(CKKS_ECACHE, "cache belongs to another context");
+  if (cfg->cache && cfg->cache->key_epoch != ctx->key_epoch)
+    return ckks::api_fail(CKKS_ESTATE, "the cache was built under keys that have since been replaced");
   if (cfg->hbm_budget_bytes < kAlign) return ckks::api_fail(CKKS_EINVAL, "hbm_budget_bytes too small");
   ckks_server *s = new ckks_server(cfg->hbm_budget_bytes, cfg->max_inflight);
   s->ctx = ctx;
+  s->key_epoch = ctx->key_epoch;
+  s->dec_limbs = ckks::limb0_decode_exact(ctx, 255.0, ckks::encryption_terms(cfg->cache), cfg->filter_k != 0) ? 1 : 2;
   s->cfg = *cfg;
   s->t0 = Clock::now();
   int dev_prev = -1;
@@ -255,6 +264,8 @@ int ckks_server_create(ckks_ctx *ctx, const ckks_server_config *cfg, ckks_server
 int ckks_server_submit(ckks_server *s, const uint8_t *host_px, uint32_t H, uint32_t W, const uint64_t job_seed[2],
                        uint64_t first_index, double *host_out, uint64_t *job_id) {
   if (!s || !host_px || !host_out || !job_seed) return ckks::api_fail(CKKS_EINVAL, "NULL argument");
+  if (s->key_epoch != s->ctx->key_epoch)
+    return ckks::api_fail(CKKS_ESTATE, "the keys were replaced after the server was created");
   const uint64_t n = (uint64_t)H * W;
   if (n == 0 || n > 0xFFFFFFFFull) return ckks::api_fail(CKKS_EINVAL, "H*W must be in 1..2^32-1");
   const uint64_t bytes = job_bytes(s, n);

@@ -1,12 +1,13 @@
 """GPU tests of batched images (flat index space, ring buffer, fused brightness, HIP
 graph replay) and of the autotuner.
 
-The batched pipeline must give, bit for bit, the decrypted values of the unbatched
-calls: encrypt (cached or plain) -> add_const with each image's b -> decrypt, whose
-ciphertexts the parity tests pin to the CPU oracle.  Equal decrypted doubles for every
-ciphertext mean equal ciphertext residues here (any residue difference changes the
-decoded value by far more than rounding).  Graph replays are checked one by one against
-the eager result, with unrelated eager work and synchronizations between them.
+The batched ciphertexts -- encryption (value cache or plain) with each image's brightness
+fused into the gather or the encryption kernel -- are compared residue by residue, on
+every limb, with the oracle's encryption (or cached encryption) followed by its add_const,
+and the batch's decrypted values with the oracle's decryption of those ciphertexts.  The
+decrypted values also equal the unbatched calls (encrypt -> add_const -> decrypt) bit for
+bit.  Graph replays are checked one by one against the eager result, with unrelated eager
+work and synchronizations between them.
 """
 import sys
 
@@ -85,6 +86,58 @@ def test_batch_matches_unbatched(env, kind, chunk):
     assert np.array_equal(got, ref)
     assert np.max(np.abs(got - (px.astype(np.float64) + per_ct))) < 1e-3
     plan.close()
+
+
+@pytest.fixture(scope="module")
+def env_o(env, oracle_mod):
+    P, W, ctx = env
+    o = oracle_mod.Oracle(12, 3, 36, 30)
+    o.keygen(W.keygen_seed(3))
+    return P, W, ctx, o
+
+
+@pytest.mark.parametrize("kind,chunk", [("topk", 97), ("full", 128), ("plain", 61)])
+def test_batch_ciphertexts_match_oracle(env_o, kind, chunk):
+    import torch
+
+    P, W, ctx, o = env_o
+    imgs, b = _images(33, 4, 3, 9)
+    px, ends, per_ct = _flat(imgs, b)
+    n = px.size
+    _say("[gpu] batch vs oracle %s chunk %d: %d ciphertexts" % (kind, chunk, n))
+    px_dev = torch.from_numpy(px).cuda()
+    cseed, npool = (0xCAC4E, 33), 4
+    cache, entries, pool = None, {}, None
+    if kind != "plain":
+        pool = np.stack([o.pool_entry(u, cseed) for u in range(npool)])
+        if kind == "topk":
+            vals = o.topk(o.histogram(px), 20)
+            cache = ctx.cache_build(P.CKKS_CACHE_VALUE_TOPK, topk=20, zero_pool=npool, scan_px=px_dev, seed=cseed)
+        else:
+            vals = sorted(set(int(v) for v in px))
+            cache = ctx.cache_build(P.CKKS_CACHE_VALUE_FULL, zero_pool=npool, seed=cseed)
+        entries = {int(v): o.value_entry(int(v), cseed) for v in vals}
+    plan = P.BatchPlan(ctx, cache, chunk)
+    seed, first = (3, 19), 500
+    cts = ctx.empty(n)
+    dec = plan.run(px_dev, ends, b, seed, first, cts_out=cts).cpu().numpy()
+    assert cts.level == 3 and cts.scale == ctx.scale
+    got = cts.to_numpy().reshape(n, -1)
+    plain = o.encrypt_batch(px, seed, first_index=first)
+    bad = []
+    for t in range(n):
+        p = int(px[t])
+        base = plain[t] if p not in entries else o.value_encrypt(entries[p], pool, npool, p, seed, first + t)
+        ref = o.add_const(base, float(per_ct[t]))
+        if not np.array_equal(got[t], ref):
+            bad.append(t)
+        elif t % 7 == 0:
+            assert abs(dec[t] - o.decrypt(ref)) < 1e-9, t
+    assert not bad, "ciphertexts differing from the oracle: %s" % bad[:10]
+    assert np.max(np.abs(dec - (px.astype(np.float64) + per_ct))) < 1e-3
+    plan.close()
+    if cache is not None:
+        cache.close()
 
 
 def test_batch_graph_replays(env):

@@ -1,9 +1,10 @@
 """GPU tests of the streamed image pipeline (row tiles with recomputed halos, three
 overlapped stage streams): its decrypted output must equal, bit for bit, the whole-image
-sequence encrypt -> mean filter -> decrypt through the C ABI (whose ciphertexts and
-filter the parity tests pin to the CPU oracle), for every cache kind, window, tile
-height (including 1 row, a ragged last tile and one tile for the whole image) and
-stream count."""
+sequence encrypt -> mean filter -> decrypt through the C ABI, for every cache kind,
+window, tile height (including 1 row, a ragged last tile and one tile for the whole
+image) and stream count; and sampled outputs must equal the oracle's own computation of
+the same pixel -- the window's ciphertexts (plain, radix- or value-cached, each with its
+global index), the filter and the decryption -- within 1e-9."""
 import sys
 
 import numpy as np
@@ -78,3 +79,54 @@ def test_pipeline_errors(env):
         ctx.image_pipeline(px, 37, 23, (1, 1), 3, 8, 2)  # 2 streams
     with pytest.raises(P.CkksError):
         ctx.image_pipeline(px, 37, 23, (1, 1), 3, 0, 3)  # empty tiles
+
+
+def _oracle_window(o, kind, entries, pool, img, seed, first, y, x, k):
+    """The k x k clamp-edge window of ciphertexts around (y, x), encrypted by the oracle."""
+    H, W_ = img.shape
+    R = k // 2
+    cts = []
+    for dy in range(-R, R + 1):
+        for dx in range(-R, R + 1):
+            yy, xx = min(max(y + dy, 0), H - 1), min(max(x + dx, 0), W_ - 1)
+            t = first + yy * W_ + xx
+            p = int(img[yy, xx])
+            if kind == "plain":
+                cts.append(o.encrypt(p, seed, t))
+            elif kind == "radix":
+                cts.append(o.radix_encrypt(entries, 16, 2, p, seed, t))
+            else:
+                cts.append(o.value_encrypt(entries.get(p), pool, 16, p, seed, t) if p in entries else o.encrypt(p, seed, t))
+    return np.stack(cts)
+
+
+@pytest.mark.parametrize("kind,k,tile", [("plain", 5, 4), ("radix", 3, 8), ("value", 7, 6)])
+def test_pipeline_sampled_against_oracle(env, oracle_mod, kind, k, tile):
+    import torch
+
+    P, W, ctx, img, px, caches = env
+    H, W_ = img.shape
+    o = oracle_mod.Oracle(12, 3, 36, 30)
+    o.keygen(W.keygen_seed(5))
+    cseed = W.cache_seed(5)
+    entries, pool = None, None
+    if kind == "radix":
+        entries = o.radix_entries(16, 2, cseed)
+    elif kind == "value":
+        vals = o.topk(o.histogram(img.reshape(-1)), 64)
+        entries = {int(v): o.value_entry(int(v), cseed) for v in vals}
+        pool = np.stack([o.pool_entry(u, cseed) for u in range(16)])
+    seed, first = (5, 4), 23
+    _say("[gpu] pipeline vs oracle %s k=%d tile=%d" % (kind, k, tile))
+    got = ctx.image_pipeline(px, H, W_, seed, k, tile, 3, cache=caches[kind], first_index=first)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().reshape(H, W_)
+    rng = np.random.default_rng(k)
+    pts = {(0, 0), (H - 1, W_ - 1), (tile, 0), (tile - 1, W_ // 2)} | {
+        (int(a), int(b)) for a, b in zip(rng.integers(0, H, 5), rng.integers(0, W_, 5))}
+    R = k // 2
+    for (y, x) in sorted(pts):
+        win = _oracle_window(o, kind, entries, pool, img, seed, first, y, x, k)
+        ref, sc = o.mean_filter_pixel(win, k, k, k, R, R)
+        val = o.decrypt(ref, level=2, scale=sc)
+        assert abs(got[y, x] - val) < 1e-9, (y, x, got[y, x], val)

@@ -2,9 +2,11 @@
 
 Determinism: every job's decrypted pixels are bit-identical whether it runs alone or
 among other jobs admitted around it, and equal to the same pipeline called directly
-through the C ABI on one stream.  Accuracy: the decrypted filter output matches the
-plaintext clamp-edge box filter of the job's pixels.  Admission: the device bytes in
-use never exceed the budget and oversized jobs are refused.
+through the C ABI on one stream.  Parity: sampled outputs of jobs run in the mix equal the
+oracle's own encryption (full value cache with its pool) -> filter -> decryption of the
+same pixels within 1e-9.  Accuracy: the decrypted filter output matches the plaintext
+clamp-edge box filter of the job's pixels.  Admission: the device bytes in use never
+exceed the budget and oversized jobs are refused.
 """
 import sys
 import time
@@ -143,3 +145,40 @@ def test_jobs_overlap(env):
     # overlapping jobs were admitted before earlier ones finished
     res.sort(key=lambda r: r["t_admit_us"])
     assert any(res[i + 1]["t_admit_us"] < res[i]["t_done_us"] for i in range(len(res) - 1))
+
+
+def test_mix_sampled_against_oracle(env, oracle_mod):
+    P, W, ctx, cache = env
+    o = oracle_mod.Oracle(12, 3, 36, 30)
+    o.keygen(W.keygen_seed(4))
+    cseed = W.cache_seed(4)
+    pool = np.stack([o.pool_entry(u, cseed) for u in range(16)])
+    entries = {}
+    _say("[gpu] serving mix vs oracle")
+    gaps, imgs = _jobs(W, 6, seed=91, lo=5, hi=18)
+    k = 3
+    budget = 2 * max(P.job_bytes(ctx, *im.shape, k) for im in imgs)
+    srv = P.Server(ctx, budget, max_inflight=3, filter_k=k, cache=cache)
+    ids = {}
+    for i, im in enumerate(imgs):
+        ids[srv.submit(im, (4, 5000 + i), first_index=7 * i)] = i
+    srv.drain()
+    res = {ids[r["id"]]: r for r in srv.poll(16)}
+    srv.close()
+    assert len(res) == len(imgs) and all(r["status"] == 0 for r in res.values())
+    R = k // 2
+    for i, im in enumerate(imgs):
+        H, W_ = im.shape
+        seed = (4, 5000 + i)
+        for (y, x) in {(0, 0), (H - 1, W_ - 1), (H // 2, W_ // 3)}:
+            win = []
+            for dy in range(-R, R + 1):
+                for dx in range(-R, R + 1):
+                    yy, xx = min(max(y + dy, 0), H - 1), min(max(x + dx, 0), W_ - 1)
+                    p = int(im[yy, xx])
+                    if p not in entries:
+                        entries[p] = o.value_entry(p, cseed)
+                    win.append(o.value_encrypt(entries[p], pool, 16, p, seed, 7 * i + yy * W_ + xx))
+            ref, sc = o.mean_filter_pixel(np.stack(win), k, k, k, R, R)
+            val = o.decrypt(ref, level=2, scale=sc)
+            assert abs(res[i]["pixels"][y, x] - val) < 1e-9, (i, y, x)

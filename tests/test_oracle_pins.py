@@ -345,6 +345,83 @@ def test_decode_detects_out_of_bound_value(oracle_mod):
     assert rc == -1
 
 
+def test_decrypt_exact_is_the_crt_decoding(oracle_mod):
+    # the all-limb decryption equals the limb-0 decoding while the bound holds, and its CRT
+    # integers are sympy's
+    from sympy.ntheory.modular import crt
+
+    o = oracle_mod.Oracle(8, 3, 30, 20)
+    o.keygen((4, 4))
+    for t, value in enumerate([0, 3, 128, 255]):
+        ct = o.encrypt(value, (2, 2), t)
+        assert abs(o.decrypt_exact(ct) - o.decrypt(ct)) < 1e-12 * max(1.0, value)
+    d = o.decrypt_coeffs(ct)
+    Q = math.prod(o.q)
+    xs = []
+    for j in range(o.N):
+        v, _ = crt(o.q, [int(d[i, j]) for i in range(3)])
+        v = int(v)
+        xs.append(v - Q if v > Q // 2 else v)
+    ref = math.fsum(float(x) * math.cos(math.pi * j / o.N) for j, x in enumerate(xs)) / o.scale
+    assert o.decrypt_exact(ct) == ref
+
+
+def test_decrypt_exact_recovers_a_sum_past_the_limb0_bound(oracle_mod):
+    # 300 pixels of 255 at N = 4096, scale 2^30: the summed coefficients reach 300*255*2^19,
+    # past q0/2 ~ 2^35, so limb 0 alone no longer decodes (and says so) while the CRT does
+    o = oracle_mod.Oracle(12, 3, 36, 30)
+    o.keygen((0x240903568, 1))
+    cts = o.encrypt_batch(np.full(300, 255, dtype=np.uint8), (9, 9))
+    acc = cts[0]
+    for c in cts[1:]:
+        acc = o.add(acc, c)
+    with pytest.raises(ArithmeticError):
+        o.decrypt(acc)
+    assert abs(o.decrypt_exact(acc) - 300 * 255) < 3e-3
+    m, sc = o.mul_const(cts[0], 300)
+    with pytest.raises(ArithmeticError):
+        o.decrypt(m)
+    assert abs(o.decrypt_exact(m) - 300 * 255) < 3e-2
+
+
+def _accepted_radix_pairs():
+    pairs = []
+    for r in range(2, 257):
+        for D in range(1, 9):
+            if r ** (D - 1) <= 255 and r ** D >= 256:
+                pairs.append((r, D))
+    return pairs
+
+
+def test_radix_randomness_for_every_digit_count(oracle_mod):
+    # Sec. 3.3 draws one randomness bit per radix above the lowest.  For every base with two or
+    # more digits (what the library accepts), two encryptions of one pixel value whose bits differ
+    # are different ciphertexts that decrypt to the same value; with a single digit (base 256,
+    # which the library refuses) equal pixels always give the same ciphertext.
+    o = oracle_mod.Oracle(5, 2, 30, 20)
+    o.keygen((6, 6))
+    job = (2, 3)
+    words = [oracle_mod.stream_word(job, t, oracle_mod.TAG_AUX, 1) for t in range(64)]
+    for r, D in _accepted_radix_pairs():
+        E = o.radix_entries(r, D, (0xCAC4E, r))
+        mask = (1 << (D - 1)) - 1
+        if D == 1:
+            a, b = o.radix_encrypt(E, r, D, 200, job, 0), o.radix_encrypt(E, r, D, 200, job, 1)
+            assert np.array_equal(a, b), (r, D)
+            continue
+        t1 = 0
+        t2 = next(t for t in range(1, 64) if (words[t] & mask) != (words[t1] & mask))
+        a, b = o.radix_encrypt(E, r, D, 200, job, t1), o.radix_encrypt(E, r, D, 200, job, t2)
+        assert not np.array_equal(a, b), (r, D)
+        qs = np.array(o.q, dtype=object)[:, None]
+        da, db = o.decrypt_coeffs(a).astype(object), o.decrypt_coeffs(b).astype(object)
+        # both are 200 times Enc(1) plus encryptions of zero: their difference decrypts to noise only
+        diff = (da - db) % qs
+        diff = np.where(diff > qs // 2, diff - qs, diff)
+        assert np.max(np.abs(diff.astype(float))) < 1e6, (r, D)
+    assert (256, 1) in _accepted_radix_pairs() and all(D >= 2 for r, D in _accepted_radix_pairs() if r < 256)
+
+
 # ---------------------------------------------------------------------------
 # homomorphic operations
 # ---------------------------------------------------------------------------
