@@ -242,6 +242,20 @@ int ckks_cache_import(ckks_ctx *ctx, const ckks_cache_desc *desc, uint32_t n_ent
 int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
                         const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream);
 
+/* The same cached encryption for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): it calls no
+ * hipMalloc, hipFree or allocating routine.  Its per-pixel metadata lives in a fixed
+ * device array of 32 MiB that the library holds on each GPU it runs on until the process
+ * ends (ckks_encrypt_cached_noalloc_max_pixels gives the largest n for a cache: about
+ * 2.7 million pixels for a value cache, 2 million for a radix cache); a larger n is
+ * CKKS_ENOMEM_BUDGET before anything is enqueued.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (on different streams, or from different
+ * threads without ordering) race and may produce wrong ciphertexts: order them.  Results
+ * equal ckks_encrypt_cached bit for bit. */
+int ckks_encrypt_cached_noalloc(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
+                                const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream);
+uint64_t ckks_encrypt_cached_noalloc_max_pixels(const ckks_cache *cache);
+
 /* ---- homomorphic operations (Sec. 2.2.3) ---- */
 
 /* out = a + b (ckks_add) or a - b (ckks_sub), residue-wise.  a and b must have the

@@ -115,6 +115,9 @@ _SIGS = {
                                     C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_void_p)]),
     "ckks_encrypt_cached": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64),
                                       C.c_uint64, C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_encrypt_cached_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64),
+                                              C.c_uint64, C.POINTER(ckks_ct_batch_t), C.c_void_p]),
+    "ckks_encrypt_cached_noalloc_max_pixels": (C.c_uint64, [C.c_void_p]),
     "ckks_add": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.POINTER(ckks_ct_batch_t),
                            C.POINTER(ckks_ct_batch_t), C.c_void_p]),
     "ckks_sub": (C.c_int, [C.c_void_p, C.POINTER(ckks_ct_batch_t), C.POINTER(ckks_ct_batch_t),

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -82,6 +83,28 @@ void free_tables(ckks_ctx *c) {
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Fixed device scratch of ckks_encrypt_cached_noalloc: one copy per GPU the library runs
+// on, held until the process ends.  In host code `scratch` names a host-side stand-in, not
+// the device array: its device address comes from hipGetSymbolAddress, resolved once per
+// device (with that device current) when a context is created there.
+constexpr uint64_t kNoAllocScratchBytes = 32ull << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev`, or NULL if it cannot be resolved.
+void *noalloc_scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 uint64_t ct_words(const ckks_ctx *c, uint32_t level) { return (uint64_t)2 * level * (uint64_t)c->N; }
 
@@ -353,6 +376,7 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
     delete c;
     return hip_fail(e, "uploading tables");
   }
+  c->noalloc_scratch = noalloc_scratch_address(device);  // with `device` current (DeviceGuard)
   *out = c;
   return CKKS_OK;
 }
@@ -784,6 +808,44 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
   HIP_TRY(encrypt_cached_ws(ctx, cache, d_px, n, seed[0], seed[1], first_index, out->data, ws, st), "cached encryption");
   HIP_TRY(hipFreeAsync(ws, st), "workspace free");
   return CKKS_OK;
+}
+
+int ckks_encrypt_cached_noalloc(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
+                                const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream) {
+  int rc = check_keys(ctx);
+  if (rc) return rc;
+  if ((rc = check_cache(ctx, cache))) return rc;
+  if (!seed || !out) return fail(CKKS_EINVAL, "seed/out is NULL");
+  if (n && !d_px) return fail(CKKS_EINVAL, "pixel pointer is NULL");
+  if (n > 0xFFFFFFFFull) return fail(CKKS_EINVAL, "at most 2^32-1 pixels per call");
+  const uint64_t need = cached_ws_bytes(cache, n);
+  if (need > kNoAllocScratchBytes)
+    return fail(CKKS_ENOMEM_BUDGET, "%llu pixels need %llu bytes of scratch, the fixed array holds %llu",
+                (unsigned long long)n, (unsigned long long)need, (unsigned long long)kNoAllocScratchBytes);
+  if ((rc = check_out(ctx, out, n, (uint32_t)ctx->prm.L))) return rc;
+  if (!ctx->noalloc_scratch) return fail(CKKS_EDEVICE, "the fixed scratch array has no device address");
+  out->count = n;
+  out->level = (uint32_t)ctx->prm.L;
+  out->scale = ctx->scale;
+  if (n == 0) return CKKS_OK;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(encrypt_cached_ws(ctx, cache, d_px, n, seed[0], seed[1], first_index, out->data, ctx->noalloc_scratch,
+                            as_stream(stream)),
+          "cached encryption");
+  return CKKS_OK;
+}
+
+uint64_t ckks_encrypt_cached_noalloc_max_pixels(const ckks_cache *cache) {
+  if (!cache) return 0;
+  uint64_t lo = 0, hi = 0xFFFFFFFFull;
+  while (lo < hi) {  // largest n whose scratch fits (cached_ws_bytes grows with n)
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (cached_ws_bytes(cache, mid) <= kNoAllocScratchBytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 static bool overlaps(const uint64_t *a, uint64_t an, const uint64_t *b, uint64_t bn) {

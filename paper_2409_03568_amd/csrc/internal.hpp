@@ -105,6 +105,7 @@ struct ckks_ctx {
   uint64_t key_epoch = 0;
   hipStream_t pipe[3] = {nullptr, nullptr, nullptr};  // image pipeline stages, created on first use
   hipMemPool_t pool = nullptr;  // stream-ordered scratch that keeps its memory between calls
+  void *noalloc_scratch = nullptr;  // this device's fixed scratch array (ckks_encrypt_cached_noalloc)
 };
 
 
