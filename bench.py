@@ -26,7 +26,7 @@ PEAK_VALU_OPS = 256 * 64 * 2.4e9
 # Sources of the plain-encryption kernel; the HBM traffic measured with hardware counters
 # (profiles/c2_step_hbm_counters.md) is reported only while they are unchanged.
 ENC_SOURCES = ["paper_2409_03568_amd/csrc/" + f for f in
-               ("k_ntt_impl.hpp", "k_ntt_13.hip", "ntt.hpp", "modarith.hpp", "philox.hpp", "internal.hpp")]
+               ("k_ntt_impl.hpp", "k_ntt_13_enc.hip", "ntt.hpp", "modarith.hpp", "philox.hpp", "internal.hpp")]
 COUNTERS_MD = os.path.join(ROOT, "profiles", "c2_step_hbm_counters.md")
 
 

@@ -349,13 +349,22 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out);
  * [seg_end[i-1], seg_end[i])), adds each image's brightness constant b_i
  * (add_const, Sec. 4.4.2: encode(b_i) in slot 0 of c0), and decrypts every ciphertext
  * (Sec. 2.2.2) -- the batched form of encrypt -> brighten -> decrypt.  Ciphertexts are
- * produced chunk by chunk into a ring buffer of chunk_cts ciphertexts owned by the plan
- * (each fully materialized, all limbs, before it is decrypted), so device memory stays
- * bounded whatever the batch size.  With a value cache, hits are assembled by the
- * gather kernel with the brightness fused in, misses by the plain encryption kernel over
- * a compacted list; without a cache every pixel is plain-encrypted with the brightness
- * fused in.  Results equal ckks_encrypt_cached / ckks_encrypt_pixels followed by
- * ckks_add_const and ckks_decrypt_pixels, bit for bit.
+ * written, each in full (all limbs) before it is decrypted, into a ring buffer of
+ * chunk_cts ciphertexts owned by the plan, so device memory stays bounded whatever the
+ * batch size.  The cache metadata of the whole batch comes first, so hits are grouped by
+ * pool member and cache slot over all images (each pair's entries are read from L2 for
+ * all its pixels); then one persistent launch assembles every ciphertext -- entry + pool
+ * member for a cached value, full encryption for a miss or for every pixel without a
+ * cache -- with the brightness fused in, writes it to the ring (a workgroup reuses its
+ * slots in turn) and decrypts it from the registers that hold its limb-0 rows.  With a
+ * VALUE_FULL cache the launch has no encryption path and needs only the decryption's LDS
+ * and registers, so several workgroups share a CU.  (Where limb 0 alone does not decode
+ * exactly, chunks of chunk_cts ciphertexts are produced and then decrypted from the ring
+ * with the two-limb lift.)  Ciphertexts equal ckks_encrypt_cached / ckks_encrypt_pixels
+ * followed by ckks_add_const, bit for bit; the decrypted values equal ckks_decrypt_pixels
+ * of those ciphertexts bit for bit when the context's encryption and decryption use the
+ * same NTT width (the decoded sum's rounding follows the workgroup shape), otherwise to a
+ * few units in the last place.  A plan runs one batch at a time.
  * With use_graph, the whole chunk sequence is captured once into a HIP graph and
  * replayed while ckks_batch_run is called again with the same arguments.
  */

@@ -10,8 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libckks_mi355x.so")
-SOURCES = ["api.cpp", "host_math.cpp", "k_ntt_dispatch.cpp", "k_ntt_11.hip", "k_ntt_12.hip", "k_ntt_13.hip",
-           "k_ntt_14.hip", "k_ops.hip", "k_cache.hip", "server.cpp", "batch.cpp", "pipeline.cpp"]
+SOURCES = ["api.cpp", "host_math.cpp", "k_ntt_dispatch.cpp", "k_ops.hip", "k_cache.hip", "server.cpp", "batch.cpp",
+           "pipeline.cpp"] + ["k_ntt_%d_%s.hip" % (n, part) for n in (13, 12, 14, 11) for part in ("fused", "enc", "mul")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
@@ -48,7 +48,7 @@ def _compile(src: str, force: bool = True) -> str:
 def build(verbose: bool = False, force: bool = True) -> str:
     """Compile every source (force=False: only those older than their inputs) and link."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(SOURCES))) as ex:
         objs = list(ex.map(lambda src: _compile(src, force), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]

@@ -182,12 +182,12 @@ static uint64_t ws_align(uint64_t x) { return (x + 255) / 256 * 256; }
 
 uint64_t cached_ws_bytes(const ckks_cache *cache, uint64_t n) {
   if (cache->kind == CKKS_CACHE_RADIX) return ws_align(n * kMaxDigits * sizeof(int16_t)) + 256;
-  return 3 * ws_align(n * sizeof(uint32_t)) + ws_align((2 + (uint64_t)value_buckets(cache)) * sizeof(uint32_t));
+  return 3 * ws_align(n * sizeof(uint32_t)) + ws_align(value_counter_words(cache) * sizeof(uint32_t));
 }
 
 hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t seed0, uint64_t seed1, uint64_t first_index, uint64_t *out, void *ws,
-                             hipStream_t st) {
+                             hipStream_t st, bool concurrent) {
   uint8_t *w = static_cast<uint8_t *>(ws);
   if (cache->kind == CKKS_CACHE_RADIX) {
     int16_t *meta = reinterpret_cast<int16_t *>(w);
@@ -201,7 +201,6 @@ hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const
   uint32_t *hits = reinterpret_cast<uint32_t *>(w + 2 * a);
   uint32_t *counters = reinterpret_cast<uint32_t *>(w + 3 * a);
   hipError_t e = launch_value_meta(ctx, cache, px, n, first_index, seed0, seed1, meta, miss, counters, hits, st);
-  if (e == hipSuccess) e = launch_value_gather(ctx, cache, meta, counters, hits, n, out, nullptr, st);
   if (e != hipSuccess) return e;
   EncJob job;
   job.px = px;
@@ -212,7 +211,29 @@ hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const
   job.seed0 = seed0;
   job.seed1 = seed1;
   job.out = out;
-  return launch_encrypt(ctx, job, std::min<uint64_t>(n, kListGrid), st);
+  if (cache->kind == CKKS_CACHE_VALUE_FULL)  // every value is cached: no misses
+    return launch_value_gather(ctx, cache, meta, counters, hits, n, out, nullptr, st);
+  if (!concurrent || !ctx->aux) {
+    e = launch_value_gather(ctx, cache, meta, counters, hits, n, out, nullptr, st);
+    return e == hipSuccess ? launch_encrypt(ctx, job, std::min<uint64_t>(n, kListGrid), st) : e;
+  }
+  // The misses (compute-bound full encryptions) run on the auxiliary stream beside the hit
+  // gather (bound by HBM writes); both grids are bounded so that every CU holds one
+  // encryption workgroup and two gather workgroups at once.
+  hipEvent_t fork = nullptr, join = nullptr;
+  e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux, fork, 0);
+  if (e == hipSuccess) e = launch_encrypt(ctx, job, std::min<uint64_t>(n, (uint64_t)ctx->num_cus), ctx->aux);
+  if (e == hipSuccess) e = hipEventRecord(join, ctx->aux);
+  if (e == hipSuccess)
+    e = launch_value_gather(ctx, cache, meta, counters, hits, n, out, nullptr, st, 2 * (uint64_t)ctx->num_cus);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+  // events may be destroyed while their work is pending; the runtime releases them after
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  return e;
 }
 
 int filter_multiplier(const ckks_ctx *c, uint32_t level, double scale, uint32_t k, std::vector<uint64_t> &K,
@@ -377,6 +398,9 @@ int ckks_context_create(const ckks_params *params, int device, ckks_ctx **out) {
     return hip_fail(e, "uploading tables");
   }
   c->noalloc_scratch = noalloc_scratch_address(device);  // with `device` current (DeviceGuard)
+  if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->num_cus < 1)
+    c->num_cus = 1;
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) c->aux = nullptr;
   *out = c;
   return CKKS_OK;
 }
@@ -387,6 +411,7 @@ void ckks_context_destroy(ckks_ctx *ctx) {
   (void)hipDeviceSynchronize();
   for (hipStream_t &st : ctx->pipe)
     if (st) (void)hipStreamDestroy(st);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   free_tables(ctx);
   if (ctx->pool) (void)hipMemPoolDestroy(ctx->pool);
   delete ctx;
@@ -805,7 +830,8 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
   hipStream_t st = as_stream(stream);
   void *ws = nullptr;
   HIP_TRY(hipMallocFromPoolAsync(&ws, cached_ws_bytes(cache, n), ctx->pool, st), "workspace alloc");
-  HIP_TRY(encrypt_cached_ws(ctx, cache, d_px, n, seed[0], seed[1], first_index, out->data, ws, st), "cached encryption");
+  HIP_TRY(encrypt_cached_ws(ctx, cache, d_px, n, seed[0], seed[1], first_index, out->data, ws, st, true),
+          "cached encryption");
   HIP_TRY(hipFreeAsync(ws, st), "workspace free");
   return CKKS_OK;
 }
@@ -830,7 +856,7 @@ int ckks_encrypt_cached_noalloc(ckks_ctx *ctx, const ckks_cache *cache, const ui
   if (n == 0) return CKKS_OK;
   DeviceGuard g(ctx->device);
   HIP_TRY(encrypt_cached_ws(ctx, cache, d_px, n, seed[0], seed[1], first_index, out->data, ctx->noalloc_scratch,
-                            as_stream(stream)),
+                            as_stream(stream), false),
           "cached encryption");
   return CKKS_OK;
 }

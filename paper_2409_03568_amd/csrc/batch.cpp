@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "internal.hpp"
@@ -54,10 +55,11 @@ struct ckks_batch_plan {
   const ckks_cache *cache = nullptr;
   ckks_batch_config cfg{};
   uint64_t *ring = nullptr;      // [chunk][2][L][N]
-  uint32_t *meta = nullptr;      // [chunk]
-  uint32_t *miss = nullptr;      // [chunk]
-  uint32_t *hits = nullptr;      // [chunk]
-  uint32_t *counters = nullptr;  // [2 + pool * slots]
+  uint32_t *meta = nullptr;      // [px_cap] per-pixel cache metadata
+  uint32_t *miss = nullptr;      // [px_cap]
+  uint32_t *hits = nullptr;      // [px_cap]
+  uint64_t px_cap = 0;
+  uint32_t *counters = nullptr;  // value_counter_words(cache), or kCountersHead without a cache
   uint64_t *seg_end = nullptr;   // [seg_cap]
   double *seg_b = nullptr;       // [seg_cap]
   uint32_t seg_cap = 0;
@@ -87,38 +89,59 @@ void free_plan(ckks_batch_plan *p) {
   delete p;
 }
 
-// Enqueues every chunk of one run on stream st (which may be capturing).
-hipError_t enqueue_chunks(ckks_batch_plan *p, const RunKey &k, uint32_t n_seg, hipStream_t st) {
+// Enqueues one run on stream st (which may be capturing).
+//
+// When limb 0 decodes exactly (the usual case), the whole batch is one pass: with a cache,
+// the metadata of every pixel is computed first, so that the hit list is ordered by pool
+// member and cache slot over the whole batch and each (entry, pool member) pair is read
+// from L2 for all its pixels at once; then one persistent launch assembles every
+// ciphertext -- cache hit, or full encryption of a miss or of every pixel without a cache
+// -- with the brightness fused in, writes it in full to a slot of the ring (of chunk_cts
+// ciphertexts, or of cts_out) and decrypts it from the registers holding its limb-0 rows.
+// With a cache that holds every value the launch has no encryption path: its workgroups
+// need only the decryption's LDS and registers, so several share a CU and one streams
+// while another transforms.  Otherwise the batch goes chunk by chunk through the ring,
+// each chunk decrypted from it with the two-limb lift.
+hipError_t enqueue_run(ckks_batch_plan *p, const RunKey &k, uint32_t n_seg, hipStream_t st) {
   const ckks_ctx *c = p->ctx;
-  const uint64_t chunk = p->cfg.chunk_cts;
   const uint64_t S = 2 * (uint64_t)c->prm.L * (uint64_t)c->N;
+  const bool misses = !p->cache || p->cache->kind != CKKS_CACHE_VALUE_FULL;
+  const bool whole = k.dec_limbs == 1;
+  const uint64_t chunk = whole ? k.n : p->cfg.chunk_cts;
   for (uint64_t first = 0; first < k.n; first += chunk) {
     const uint64_t cnt = k.n - first < chunk ? k.n - first : chunk;
-    uint64_t *ring = k.cts ? k.cts + first * S : p->ring;
-    EncJob job;
+    FusedJob job;
     job.px = k.px + first;
     job.n = cnt;
     job.first_index = k.first_index + first;
     job.seed0 = k.seed[0];
     job.seed1 = k.seed[1];
-    job.out = ring;
+    job.out = k.cts ? k.cts + first * S : p->ring;
     job.seg_end = p->seg_end;
     job.seg_b = p->seg_b;
     job.n_seg = n_seg;
     job.seg_base = first;
     job.bright_scale = ldexp(c->scale, 1 - c->prm.log_n);
-    hipError_t e;
+    job.cursor = p->counters + 2;
+    if (whole) {
+      job.dec_out = k.out;
+      job.inv_scale = 1.0 / c->scale;
+      job.ring = k.cts ? 0 : p->cfg.chunk_cts;
+    }
+    hipError_t e = hipSuccess;
     if (p->cache) {
       e = launch_value_meta(c, p->cache, job.px, cnt, job.first_index, job.seed0, job.seed1, p->meta, p->miss,
                             p->counters, p->hits, st);
-      if (e == hipSuccess) e = launch_value_gather(c, p->cache, p->meta, p->counters, p->hits, cnt, ring, &job, st);
-      job.list = p->miss;
-      job.list_count = p->counters;
-      if (e == hipSuccess) e = launch_encrypt(c, job, cnt < kListGrid ? cnt : kListGrid, st);
-    } else {
-      e = launch_encrypt(c, job, cnt < (1u << 24) ? cnt : (1u << 24), st);
+      job.counters = p->counters;
+      job.miss_list = p->miss;
+      job.hits = p->hits;
+      job.meta = p->meta;
+      job.entries = p->cache->entries;
+      job.pool = p->cache->pool_cts;
     }
-    if (e == hipSuccess) e = launch_decrypt(c, ring, cnt, c->prm.L, c->scale, k.out + first, k.dec_limbs, st);
+    if (e == hipSuccess) e = launch_cached_fused(c, job, misses, st);
+    if (e == hipSuccess && !whole)
+      e = launch_decrypt(c, job.out, cnt, c->prm.L, c->scale, k.out + first, k.dec_limbs, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -146,11 +169,9 @@ int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_ba
   p->cfg = *cfg;
   const uint64_t chunk = cfg->chunk_cts;
   hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->ring), chunk * ckks_ct_bytes(ctx, (uint32_t)ctx->prm.L));
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->meta), chunk * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->miss), chunk * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->hits), chunk * sizeof(uint32_t));
   if (e == hipSuccess)
-    e = hipMalloc(reinterpret_cast<void **>(&p->counters), (2 + (size_t)(cache ? value_buckets(cache) : 0)) * sizeof(uint32_t));
+    e = hipMalloc(reinterpret_cast<void **>(&p->counters),
+                  (cache ? value_counter_words(cache) : kCountersHead) * sizeof(uint32_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     free_plan(p);
@@ -225,16 +246,28 @@ int ckks_batch_run(ckks_batch_plan *p, const uint8_t *d_px, uint64_t n, const ui
     }
     BATCH_TRY(hipMemcpy(p->seg_end, host_seg_end, n_seg * sizeof(uint64_t), hipMemcpyHostToDevice), "segment upload");
     BATCH_TRY(hipMemcpy(p->seg_b, host_seg_b, n_seg * sizeof(double), hipMemcpyHostToDevice), "segment upload");
+    // per-pixel cache metadata for the whole batch (or one chunk on the two-limb path)
+    const uint64_t need = p->cache ? (k.dec_limbs == 1 ? n : std::min<uint64_t>(n, p->cfg.chunk_cts)) : 0;
+    if (need > p->px_cap) {
+      for (uint32_t **q : {&p->meta, &p->miss, &p->hits}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+      }
+      p->px_cap = 0;
+      for (uint32_t **q : {&p->meta, &p->miss, &p->hits})
+        BATCH_TRY(hipMalloc(reinterpret_cast<void **>(q), need * sizeof(uint32_t)), "metadata alloc");
+      p->px_cap = need;
+    }
   }
   if (!p->cfg.use_graph || !same) {
     // eager launch: the first run with new arguments (and every run without graphs)
-    BATCH_TRY(enqueue_chunks(p, k, n_seg, st), "batch launch");
+    BATCH_TRY(enqueue_run(p, k, n_seg, st), "batch launch");
     p->key = k;
     p->have_key = true;
     if (!p->cfg.use_graph) return CKKS_OK;
     // record the same sequence for the next runs with these arguments (capture does not execute it)
     BATCH_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-    const hipError_t e = enqueue_chunks(p, k, n_seg, p->cap);
+    const hipError_t e = enqueue_run(p, k, n_seg, p->cap);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(p->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -70,6 +70,36 @@ struct EncJob {
   double bright_scale = 0.0;
 };
 
+// Cached encryption in one persistent launch (k_cached_fused): misses miss_list[0..counters[0])
+// are encrypted in full, hits hits[0..counters[1]) are entry + pool member as meta[pixel]
+// says; without a cache (counters == NULL) every pixel 0..n-1 is encrypted in full.
+// Optional fused brightness (seg_* as in EncJob) and decryption of limb 0 into dec_out.
+struct FusedJob {
+  const uint8_t *px = nullptr;
+  uint64_t n = 0;
+  uint64_t first_index = 0;
+  uint64_t seed0 = 0, seed1 = 0;
+  uint64_t *out = nullptr;               // [n][2][L][N]
+  const uint32_t *counters = nullptr;    // [miss count, hit count], or NULL: every pixel a miss
+  const uint32_t *miss_list = nullptr;
+  const uint32_t *hits = nullptr;
+  const uint32_t *meta = nullptr;
+  const uint64_t *entries = nullptr;
+  const uint64_t *pool = nullptr;
+  const uint64_t *seg_end = nullptr;
+  const double *seg_b = nullptr;
+  uint32_t n_seg = 0;
+  uint64_t seg_base = 0;
+  double bright_scale = 0.0;
+  uint32_t *cursor = nullptr;            // [kXcds] work cursors, zeroed by the launcher
+  double *dec_out = nullptr;             // [n] decrypted slot 0 (limb 0), or NULL
+  double inv_scale = 0.0;
+  // ring = 0: the ciphertext of pixel t goes to out + t S.  Otherwise out holds `ring`
+  // ciphertexts and the one produced at position i of the launch's item sequence goes to
+  // slot i mod ring (only with dec_out: the ciphertexts are written in full but not kept).
+  uint64_t ring = 0;
+};
+
 // Image of flat pixel index g: the first i with g < seg_end[i] (seg_end ascending, last = total).
 CKKS_SEG_HD inline uint32_t segment_of(const uint64_t *seg_end, uint32_t n_seg, uint64_t g) {
   uint32_t lo = 0, hi = n_seg - 1;
@@ -105,6 +135,8 @@ struct ckks_ctx {
   uint64_t key_epoch = 0;
   hipStream_t pipe[3] = {nullptr, nullptr, nullptr};  // image pipeline stages, created on first use
   hipMemPool_t pool = nullptr;  // stream-ordered scratch that keeps its memory between calls
+  int num_cus = 1;              // compute units of the device (bounded, co-resident grids)
+  hipStream_t aux = nullptr;    // second stream of cached encryption (misses beside the hit gather)
   void *noalloc_scratch = nullptr;  // this device's fixed scratch array (ckks_encrypt_cached_noalloc)
 };
 
@@ -131,6 +163,14 @@ inline uint32_t value_slot_buckets(const ckks_cache *cache) {
   return (uint64_t)cache->pool * cache->n_slots <= 65536 ? cache->n_slots : 1u;
 }
 inline uint32_t value_buckets(const ckks_cache *cache) { return cache->pool * value_slot_buckets(cache); }
+// Blocks of 1024 buckets of the two-level hit-count scan.
+inline uint32_t value_scan_blocks(const ckks_cache *cache) { return (value_buckets(cache) + 1023) / 1024; }
+// Value-cache counters: [0] miss count, [1] hit count, [2..10) the per-XCD work cursors
+// of the gather (see xcd_claim), then the bucket cursors and the scan's block offsets.
+constexpr uint32_t kCountersHead = 10;
+inline uint64_t value_counter_words(const ckks_cache *cache) {
+  return kCountersHead + (uint64_t)value_buckets(cache) + value_scan_blocks(cache);
+}
 
 namespace ckks {
 
@@ -145,9 +185,11 @@ int filter_multiplier(const ckks_ctx *c, uint32_t level, double scale, uint32_t 
 // bytes of device memory, 256-byte aligned): value caches gather hits and plain-encrypt
 // misses, radix caches combine their entries.
 uint64_t cached_ws_bytes(const ckks_cache *cache, uint64_t n);
+// With `concurrent`, a value cache's misses run on the context's auxiliary stream beside the
+// hit gather (forked from and joined back into `stream` by events).
 hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t seed0, uint64_t seed1, uint64_t first_index, uint64_t *out, void *ws,
-                             hipStream_t stream);
+                             hipStream_t stream, bool concurrent);
 
 // Number of fresh-encryption error terms a ciphertext of this cache kind carries (1 for
 // plain encryption, cache == NULL).
@@ -160,13 +202,18 @@ double encryption_terms(const ckks_cache *cache);
 bool limb0_decode_exact(const ckks_ctx *c, double value_bound, double terms, bool filtered);
 
 // Launchers (return a hipError_t; enqueue on `stream`).
+// misses = false: the cache holds every value (VALUE_FULL), so only hits occur; the kernel
+// is then compiled without the encryption path (decryption-sized LDS and registers) and
+// uses the decryption's NTT width.
+hipError_t launch_cached_fused(const ckks_ctx *c, const FusedJob &job, bool misses, hipStream_t stream);
 hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
 hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream);
 hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream);
 // limbs = 1: decode the centered residue of limb 0; limbs = 2 (level >= 2): decode the
-// centered CRT lift of limbs 0 and 1.
+// centered CRT lift of limbs 0 and 1.  max_grid (0 = no bound): at most this many
+// workgroups, each taking every max_grid-th ciphertext.
 hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
-                          int limbs, hipStream_t stream);
+                          int limbs, hipStream_t stream, uint64_t max_grid = 0);
 // Key-switching keys of s^2 (grid: digits x primes), then their NTT-domain copies.
 hipError_t launch_relin_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream);
 hipError_t launch_relin_prepare(const ckks_ctx *c, hipStream_t stream);
@@ -192,6 +239,8 @@ hipError_t launch_rescale(const ckks_ctx *c, const uint64_t *a, uint64_t *out, u
 hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
                               uint32_t y0, uint32_t y1, uint32_t k, int level, const uint64_t *K, hipStream_t stream);
 
+// Fills n words with v (a kernel, so it can be captured in a graph).
+hipError_t launch_fill_u32(uint32_t *p, uint32_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t n, uint32_t topk, uint32_t *hist,
                                  ckks_cache *cache, hipStream_t stream);
 // Value-cache metadata for n pixels: meta[t], the miss list, and the hit list grouped by
@@ -199,9 +248,10 @@ hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t 
 hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t first_index, uint64_t seed0, uint64_t seed1, uint32_t *meta,
                              uint32_t *miss_list, uint32_t *counters, uint32_t *hits, hipStream_t stream);
+// max_grid (0 = no bound): at most this many workgroups, walking the hit list persistently.
 hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta,
-                               const uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
-                               const EncJob *bright, hipStream_t stream);
+                               uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
+                               const EncJob *bright, hipStream_t stream, uint64_t max_grid = 0);
 hipError_t launch_radix_meta(const ckks_ctx *c, const ckks_cache *cache, const uint8_t *px, uint64_t n,
                              uint64_t first_index, uint64_t seed0, uint64_t seed1, int16_t *meta, uint32_t *bad,
                              hipStream_t stream);
@@ -220,6 +270,28 @@ __device__ __forceinline__ uint32_t xcd_logical_block(uint32_t b, uint32_t nb) {
   const uint32_t x = b % kXcds, i = b / kXcds;
   const uint32_t per = nb / kXcds, rem = nb % kXcds;
   return x * per + (x < rem ? x : rem) + i;
+}
+
+// Dynamic work claiming for persistent kernels whose items are ordered for cache locality
+// (the bucketed hit list): the item range [0, total) is cut into one contiguous region per
+// XCD; the workgroups of XCD x take items of region x in order from an atomic cursor, then
+// help with the other regions in turn.  All workgroups of an XCD thus work on neighbouring
+// items at any time, whatever their speeds, and share that XCD's L2; a static stride
+// would let them drift apart over the list.  cursor[kXcds] must start at zero.  Returns
+// the next item of this workgroup, or `total` when there is none left; `region` keeps its
+// state (start at 0).  Contains barriers: every thread of the workgroup must call it.
+__device__ __forceinline__ uint64_t xcd_claim(uint32_t *cursor, uint64_t total, uint32_t &region, uint64_t *slot) {
+  const uint32_t home = blockIdx.x % kXcds;
+  for (; region < kXcds; region++) {
+    const uint32_t x = (home + region) % kXcds;
+    const uint64_t lo = total * x / kXcds, hi = total * (x + 1) / kXcds;
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = lo + atomicAdd(&cursor[x], 1u);
+    __syncthreads();
+    const uint64_t i = *slot;
+    if (i < hi) return i;
+  }
+  return total;
 }
 
 // 16-byte vector of two residues, for non-temporal stores of ciphertext rows that are not

@@ -5,6 +5,8 @@
 // then stream the ciphertext rows, reading cache entries that stay resident in the
 // L2 / Infinity Cache and writing each output residue once.  Pixels a value cache
 // does not hold go to a compacted list that the plain encryption kernel consumes.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "modarith.hpp"
 #include "philox.hpp"
@@ -86,41 +88,56 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// Exclusive prefix sum of the per-bucket hit counts (in place: they become the bucket
-// cursors) and the total hit count.  One workgroup of kScanThreads threads.
+// Exclusive prefix sum of the per-bucket hit counts in two levels: each workgroup of
+// kScanThreads threads scans its block of buckets in place (they become the bucket cursors
+// within the block) and writes the block's total; then one small workgroup turns the block
+// totals into block offsets and the total hit count.  The scatter adds a bucket's block
+// offset to the cursor it takes.
 constexpr int kScanThreads = 1024;
-__global__ void __launch_bounds__(kScanThreads) k_bucket_scan(uint32_t *__restrict__ ucount, uint32_t npool,
-                                                              uint32_t *__restrict__ total) {
-  __shared__ uint32_t part[kScanThreads];
-  const uint32_t per = (npool + kScanThreads - 1) / kScanThreads;
-  const uint32_t lo = threadIdx.x * per, hi = min(lo + per, npool);
-  uint32_t s = 0;
-  for (uint32_t i = lo; i < hi; i++) s += ucount[i];
-  part[threadIdx.x] = s;
+__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(uint32_t *__restrict__ ucount, uint32_t nb,
+                                                              uint32_t *__restrict__ block_tot) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const uint32_t i = blockIdx.x * kScanThreads + threadIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t v = i < nb ? ucount[i] : 0u;
+  uint32_t x = v;  // inclusive scan within the wave
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t v = threadIdx.x >= (uint32_t)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t k = 0; k < w; k++) before += wsum[k];
+  if (i < nb) ucount[i] = before + x - v;
+  if (threadIdx.x == kScanThreads - 1) block_tot[blockIdx.x] = before + x;
+}
+
+// Block totals -> exclusive block offsets (in place) and the total hit count.
+__global__ void __launch_bounds__(64) k_scan_tops(uint32_t *__restrict__ block_tot, uint32_t nblk,
+                                                  uint32_t *__restrict__ total) {
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (uint32_t b = 0; b < nblk; b++) {
+      const uint32_t t = block_tot[b];
+      block_tot[b] = run;
+      run += t;
+    }
+    *total = run;
   }
-  uint32_t run = part[threadIdx.x] - s;  // exclusive prefix of this thread's range
-  for (uint32_t i = lo; i < hi; i++) {
-    const uint32_t c = ucount[i];
-    ucount[i] = run;
-    run += c;
-  }
-  if (threadIdx.x == kScanThreads - 1) *total = part[kScanThreads - 1];
 }
 
 // Hit pixels grouped by bucket (order inside a bucket is arbitrary; every output row is
 // written independently, so the result does not depend on it).
 __global__ void __launch_bounds__(kThreads)
     k_value_scatter(const uint32_t *__restrict__ meta, uint64_t n, uint32_t nslots, uint32_t npool,
-                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ hits) {
+                    uint32_t *__restrict__ cursor, const uint32_t *__restrict__ block_off, uint32_t *__restrict__ hits) {
   for (uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (uint64_t)gridDim.x * kThreads) {
     const uint32_t m = meta[t];
-    if (m != 0) hits[atomicAdd(&cursor[hit_bucket(m >> 16, (m & 0xffffu) - 1u, nslots, npool)], 1u)] = (uint32_t)t;
+    if (m != 0) {
+      const uint32_t b = hit_bucket(m >> 16, (m & 0xffffu) - 1u, nslots, npool);
+      hits[block_off[b / kScanThreads] + atomicAdd(&cursor[b], 1u)] = (uint32_t)t;
+    }
   }
 }
 
@@ -146,14 +163,16 @@ __device__ __forceinline__ uint64_t add_encoded(uint64_t z, double fb, double cj
 __global__ void __launch_bounds__(kThreads)
     k_value_gather(const uint64_t *__restrict__ entries, const uint64_t *__restrict__ pool,
                    const uint32_t *__restrict__ meta, const uint32_t *__restrict__ hits,
-                   const uint32_t *__restrict__ hit_count, int L, int log_n, const LimbConsts *__restrict__ lcp,
+                   uint32_t *__restrict__ counters, int L, int log_n, const LimbConsts *__restrict__ lcp,
                    Bright br, uint64_t *__restrict__ out) {
   const LimbConsts &lc = *lcp;
   const int N = 1 << log_n;
   const uint64_t S = (uint64_t)2 * L * N;
-  const uint64_t nh = *hit_count;
-  const uint64_t nb = gridDim.x;
-  for (uint64_t idx = xcd_logical_block(blockIdx.x, gridDim.x); idx < nh; idx += nb) {
+  const uint64_t nh = counters[1];
+  __shared__ uint64_t s_item;
+  uint32_t region = 0;
+  for (uint64_t idx = xcd_claim(counters + 2, nh, region, &s_item); idx < nh;
+       idx = xcd_claim(counters + 2, nh, region, &s_item)) {
     const uint64_t ct = hits[idx];
     const uint32_t m = meta[ct];
     const u64x2 *pe = reinterpret_cast<const u64x2 *>(entries + (uint64_t)((m & 0xffffu) - 1) * S);
@@ -273,6 +292,11 @@ static uint32_t grid_for(uint64_t items, uint64_t per_block) {
   return (uint32_t)(g == 0 ? 1 : (g < (1u << 20) ? g : (1u << 20)));
 }
 
+hipError_t launch_fill_u32(uint32_t *p, uint32_t n, uint32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_histogram_topk(const ckks_ctx *c, const uint8_t *px, uint64_t n, uint32_t topk, uint32_t *hist,
                                  ckks_cache *cache, hipStream_t st) {
   (void)c;
@@ -287,21 +311,24 @@ hipError_t launch_value_meta(const ckks_ctx *c, const ckks_cache *cache, const u
                              uint64_t first_index, uint64_t seed0, uint64_t seed1, uint32_t *meta,
                              uint32_t *miss_list, uint32_t *counters, uint32_t *hits, hipStream_t st) {
   (void)c;
-  uint32_t *miss_count = counters, *hit_count = counters + 1, *ucount = counters + 2;
-  const uint32_t nb = value_buckets(cache);
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 + nb, kThreads)), dim3(kThreads), 0, st, counters, 2u + nb, 0u);
+  uint32_t *miss_count = counters, *hit_count = counters + 1, *ucount = counters + kCountersHead;
+  const uint32_t nb = value_buckets(cache), nblk = value_scan_blocks(cache);
+  uint32_t *block_tot = ucount + nb;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(kCountersHead + nb, kThreads)), dim3(kThreads), 0, st, counters,
+                     kCountersHead + nb, 0u);
   hipLaunchKernelGGL(k_value_meta, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, px, n, first_index, seed0,
                      seed1, cache->slot_of, cache->pool, value_slot_buckets(cache), meta, miss_list, miss_count,
                      ucount);
-  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kScanThreads), 0, st, ucount, nb, hit_count);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nblk), dim3(kScanThreads), 0, st, ucount, nb, block_tot);
+  hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(64), 0, st, block_tot, nblk, hit_count);
   hipLaunchKernelGGL(k_value_scatter, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, meta, n,
-                     value_slot_buckets(cache), cache->pool, ucount, hits);
+                     value_slot_buckets(cache), cache->pool, ucount, block_tot, hits);
   return hipGetLastError();
 }
 
 hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const uint32_t *meta,
-                               const uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
-                               const EncJob *bright, hipStream_t st) {
+                               uint32_t *counters, const uint32_t *hits, uint64_t n, uint64_t *out,
+                               const EncJob *bright, hipStream_t st, uint64_t max_grid) {
   Bright br{nullptr, nullptr, 0, 0, 0.0, c->dev.cosj};
   if (bright && bright->seg_b) {
     br.seg_end = bright->seg_end;
@@ -310,9 +337,14 @@ hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const
     br.seg_base = bright->seg_base;
     br.scale = bright->bright_scale;
   }
-  // n is an upper bound of the hit count, which the kernel reads
-  hipLaunchKernelGGL(k_value_gather, dim3(grid_for(n, 1)), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
-                     meta, hits, counters + 1, c->prm.L, c->prm.log_n, c->d_lc, br, out);
+  // n is an upper bound of the hit count, which the kernel reads; a persistent grid claims
+  // the hits per XCD (the cursors were zeroed with the counters by the metadata pass), at
+  // most max_grid workgroups when another kernel is to run beside it
+  uint64_t grid = std::min<uint64_t>(n, 8 * (uint64_t)c->num_cus);
+  if (max_grid && grid > max_grid) grid = max_grid;
+  if (grid == 0) grid = 1;
+  hipLaunchKernelGGL(k_value_gather, dim3((uint32_t)grid), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
+                     meta, hits, counters, c->prm.L, c->prm.log_n, c->d_lc, br, out);
   return hipGetLastError();
 }
 

@@ -5,10 +5,11 @@ namespace ckks {
 
 #define CKKS_DECLARE_RING(LOGN)                                                                              \
   hipError_t launch_encrypt_##LOGN(const ckks_ctx *, const EncJob &, uint64_t, hipStream_t);                 \
+  hipError_t launch_cached_fused_##LOGN(const ckks_ctx *, const FusedJob &, bool, hipStream_t);              \
   hipError_t launch_keygen_##LOGN(const ckks_ctx *, uint64_t, uint64_t, hipStream_t);                        \
   hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *, hipStream_t);                                      \
   hipError_t launch_decrypt_##LOGN(const ckks_ctx *, const uint64_t *, uint64_t, int, double, double *, int,   \
-                                   hipStream_t);                                                              \
+                                   hipStream_t, uint64_t);                                                    \
   hipError_t launch_relin_keygen_##LOGN(const ckks_ctx *, uint64_t, uint64_t, hipStream_t);                  \
   hipError_t launch_relin_prepare_##LOGN(const ckks_ctx *, hipStream_t);                                     \
   hipError_t launch_mul_##LOGN(const ckks_ctx *, const uint64_t *, const uint64_t *, uint64_t *, uint64_t, int, \
@@ -30,13 +31,16 @@ CKKS_DECLARE_RING(14)
 hipError_t launch_encrypt(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t stream) {
   CKKS_RING_SWITCH(launch_encrypt, job, grid, stream)
 }
+hipError_t launch_cached_fused(const ckks_ctx *c, const FusedJob &job, bool misses, hipStream_t stream) {
+  CKKS_RING_SWITCH(launch_cached_fused, job, misses, stream)
+}
 hipError_t launch_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream) {
   CKKS_RING_SWITCH(launch_keygen, seed0, seed1, stream)
 }
 hipError_t launch_keys_prepare(const ckks_ctx *c, hipStream_t stream) { CKKS_RING_SWITCH(launch_keys_prepare, stream) }
 hipError_t launch_decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
-                          int limbs, hipStream_t stream) {
-  CKKS_RING_SWITCH(launch_decrypt, cts, n, level, scale, out, limbs, stream)
+                          int limbs, hipStream_t stream, uint64_t max_grid) {
+  CKKS_RING_SWITCH(launch_decrypt, cts, n, level, scale, out, limbs, stream, max_grid)
 }
 hipError_t launch_relin_keygen(const ckks_ctx *c, uint64_t seed0, uint64_t seed1, hipStream_t stream) {
   CKKS_RING_SWITCH(launch_relin_keygen, seed0, seed1, stream)

@@ -93,11 +93,103 @@ __device__ __forceinline__ int smp_g(uint32_t s, int shift, int B) { return (int
 // BRIGHT adds the image's brightness encoding to c0 (EncJob::seg_b).
 enum EncMode : int { kEncPixels = 0, kEncList = 1, kEncEntries = 2 };
 
+// One limb of the encryption of the current item, by the whole workgroup (the samples
+// are drawn): x = NTT(v); c0 = INTT(x pk0^) + e0 + m (+ the brightness encoding fb);
+// c1 = INTT(x pk1^) + e1, stored to out.  With KEEP the canonical values of c0 and c1 are
+// also returned in k0 / k1 (first-pass layout: register r holds coefficient tid + T r).
+template <int LOGN, int LOGR, int RC, bool BRIGHT, bool KEEP>
+__device__ __forceinline__ void encrypt_limb(int l, double *lds, const uint16_t *smpl, const uint32_t (&smp)[1 << LOGR],
+                                             int L, int B, double value, double fb, uint64_t *out,
+                                             const LimbConsts &lc, const DevTables &dt, double (&k0)[1 << LOGR],
+                                             double (&k1)[1 << LOGR]) {
+  using S = Shape<LOGN, LOGR>;
+  using Red = Schedule<LOGN, RC>;
+  constexpr int N = S::N, R = S::R, T = S::T;
+  const double q = lc.q[l], qinv = lc.qinv[l];
+  const int tid = opaque(threadIdx.x);
+  auto sample = [&](int r) -> uint32_t {
+    if constexpr (S::kSmpLds)
+      return (uint32_t)smpl[tid + T * r];
+    else
+      return smp[r];
+  };
+  double x[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) x[r] = (double)smp_t(sample(r));
+  ntt_forward<LOGN, LOGR, Red::fwd_small>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
+  // both pointwise products at once (one wait for the key loads; x is then dead and
+  // the second product takes its registers through the first inverse transform)
+  double y[R], y1[R];
+  {
+    const double *pk0 = dt.pk_hat + (size_t)l * N, *pk1 = dt.pk_hat + ((size_t)L + l) * N;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const unsigned e = elem_index<LOGN, LOGR, S::LAST>(tid, r);
+      y[r] = mulmod(x[r], ld_table(pk0, e), q, qinv);
+      y1[r] = mulmod(x[r], ld_table(pk1, e), q, qinv);
+    }
+  }
+  if constexpr (S::kDual) {
+    // c0 and c1 of this limb through one paired inverse transform; the plaintext and
+    // e0 are loaded before its final exchange
+    double add[R];
+    ntt_inverse2<LOGN, LOGR, Red::inv>(y, y1, lds, lds + S::SLOTS + kCdtSlots + 64, tid, dt.tw_inv + (size_t)l * N,
+                                       q, qinv, [&] {
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int j = tid + T * r;
+        add[r] = (double)smp_g(sample(r), kSmpShiftG2, B) + __builtin_rint(value * ld_table(dt.enc_T, j));
+        if (BRIGHT) add[r] += __builtin_rint(fb * ld_table(dt.cosj, j));
+      }
+    });
+    uint64_t *dst0 = out + (size_t)l * N, *dst1 = out + ((size_t)L + l) * N;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const unsigned c = tid + T * r;
+      const double v0 = canon(y[r] + add[r], q, qinv);
+      const double v1 = canon(y1[r] + (double)smp_g(sample(r), kSmpShiftG3, B), q, qinv);
+      __builtin_nontemporal_store(f64_to_u64(v0), word_at(dst0, c));
+      __builtin_nontemporal_store(f64_to_u64(v1), word_at(dst1, c));
+      if constexpr (KEEP) {
+        k0[r] = v0;
+        k1[r] = v1;
+      }
+    }
+    return;
+  }
+#pragma unroll 1
+  for (int poly = 0; poly < 2; poly++) {
+    if (poly == 1) {
+#pragma unroll
+      for (int r = 0; r < R; r++) y[r] = y1[r];
+    }
+    // the plaintext (poly 0) and the Gaussian term, loaded before the final exchange
+    double add[R];
+    ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, [&] {
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int j = tid + T * r;
+        add[r] = (double)smp_g(sample(r), poly == 0 ? kSmpShiftG2 : kSmpShiftG3, B);
+        if (poly == 0) {
+          add[r] += __builtin_rint(value * ld_table(dt.enc_T, j));
+          if (BRIGHT) add[r] += __builtin_rint(fb * ld_table(dt.cosj, j));
+        }
+      }
+    });
+    uint64_t *dst = out + ((size_t)poly * L + l) * N;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const double v = canon(y[r] + add[r], q, qinv);
+      __builtin_nontemporal_store(f64_to_u64(v), word_at(dst, tid + T * r));
+      if constexpr (KEEP) (poly == 0 ? k0 : k1)[r] = v;
+    }
+  }
+}
+
 template <int LOGN, int LOGR, int RC, int MODE, bool BRIGHT>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     k_encrypt(EncJob job, const LimbConsts *__restrict__ lcp, DevTables dt) {
   using S = Shape<LOGN, LOGR>;
-  using Red = Schedule<LOGN, RC>;
   constexpr int N = S::N, R = S::R, T = S::T;
   const LimbConsts &lc = *lcp;
   extern __shared__ double lds[];
@@ -122,79 +214,9 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       draw_samples<LOGN, LOGR>(smpl, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
     else
       draw_samples<LOGN, LOGR>(smp, lds16, cdt, B, opaque(tid), job.seed0, job.seed1, t, kTagV, kTagE0, kTagE1);
-    for (int l = 0; l < L; l++) {
-      const double q = lc.q[l], qinv = lc.qinv[l];
-      const int tid = opaque(threadIdx.x);
-      auto sample = [&](int r) -> uint32_t {
-        if constexpr (S::kSmpLds)
-          return (uint32_t)smpl[tid + T * r];
-        else
-          return smp[r];
-      };
-      double x[R];
-#pragma unroll
-      for (int r = 0; r < R; r++) x[r] = (double)smp_t(sample(r));
-      ntt_forward<LOGN, LOGR, Red::fwd_small>(x, lds, tid, dt.tw_fwd + (size_t)l * N, q, qinv);
-      // both pointwise products at once (one wait for the key loads; x is then dead and
-      // the second product takes its registers through the first inverse transform)
-      double y[R], y1[R];
-      {
-        const double *pk0 = dt.pk_hat + (size_t)l * N, *pk1 = dt.pk_hat + ((size_t)L + l) * N;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-          const unsigned e = elem_index<LOGN, LOGR, S::LAST>(tid, r);
-          y[r] = mulmod(x[r], ld_table(pk0, e), q, qinv);
-          y1[r] = mulmod(x[r], ld_table(pk1, e), q, qinv);
-        }
-      }
-      if constexpr (S::kDual) {
-        // c0 and c1 of this limb through one paired inverse transform; the plaintext and
-        // e0 are loaded before its final exchange
-        double add[R];
-        ntt_inverse2<LOGN, LOGR, Red::inv>(y, y1, lds, lds + S::SLOTS + kCdtSlots + 64, tid,
-                                           dt.tw_inv + (size_t)l * N, q, qinv, [&] {
-#pragma unroll
-          for (int r = 0; r < R; r++) {
-            const int j = tid + T * r;
-            add[r] = (double)smp_g(sample(r), kSmpShiftG2, B) + __builtin_rint(value * ld_table(dt.enc_T, j));
-            if (BRIGHT) add[r] += __builtin_rint(fb * ld_table(dt.cosj, j));
-          }
-        });
-        uint64_t *dst0 = out + (size_t)l * N, *dst1 = out + ((size_t)L + l) * N;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-          const unsigned c = tid + T * r;
-          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), word_at(dst0, c));
-          __builtin_nontemporal_store(f64_to_u64(canon(y1[r] + (double)smp_g(sample(r), kSmpShiftG3, B), q, qinv)),
-                                      word_at(dst1, c));
-        }
-        continue;
-      }
-#pragma unroll 1
-      for (int poly = 0; poly < 2; poly++) {
-        if (poly == 1) {
-#pragma unroll
-          for (int r = 0; r < R; r++) y[r] = y1[r];
-        }
-        // the plaintext (poly 0) and the Gaussian term, loaded before the final exchange
-        double add[R];
-        ntt_inverse<LOGN, LOGR, Red::inv>(y, lds, tid, dt.tw_inv + (size_t)l * N, q, qinv, [&] {
-#pragma unroll
-          for (int r = 0; r < R; r++) {
-            const int j = tid + T * r;
-            add[r] = (double)smp_g(sample(r), poly == 0 ? kSmpShiftG2 : kSmpShiftG3, B);
-            if (poly == 0) {
-              add[r] += __builtin_rint(value * ld_table(dt.enc_T, j));
-              if (BRIGHT) add[r] += __builtin_rint(fb * ld_table(dt.cosj, j));
-            }
-          }
-        });
-        uint64_t *dst = out + ((size_t)poly * L + l) * N;
-#pragma unroll
-        for (int r = 0; r < R; r++)
-          __builtin_nontemporal_store(f64_to_u64(canon(y[r] + add[r], q, qinv)), word_at(dst, tid + T * r));
-      }
-    }
+    double unused0[R], unused1[R];
+    for (int l = 0; l < L; l++)
+      encrypt_limb<LOGN, LOGR, RC, BRIGHT, false>(l, lds, smpl, smp, L, B, value, fb, out, lc, dt, unused0, unused1);
   }
 }
 
@@ -413,6 +435,7 @@ static hipError_t set_lds() {
 }  // namespace ckks
 
 #include "k_mul_impl.hpp"
+#include "k_fused_impl.hpp"
 
 namespace ckks {
 
@@ -439,6 +462,50 @@ struct Launch {
     }
     if (job.list_count) return hipErrorInvalidValue;
     return bright ? encrypt_as<kEncPixels, true>(c, job, grid, st) : encrypt_as<kEncPixels, false>(c, job, grid, st);
+  }
+  template <bool BRIGHT, bool DECRYPT, bool MISSES>
+  static hipError_t fused_as(const ckks_ctx *c, const FusedJob &job, hipStream_t st) {
+    constexpr auto kernel = k_cached_fused<LOGN, LOGR, RC, BRIGHT, DECRYPT, MISSES>;
+    constexpr size_t lds = MISSES ? S::enc_lds_bytes : DECRYPT ? S::lds_bytes : 0;
+    hipError_t e = set_lds<LOGN, LOGR, kernel, lds>();
+    if (e != hipSuccess) return e;
+    // a persistent grid: the workgroups that fit on the device at once
+    static std::atomic<int> resident{0};
+    int g = resident.load(std::memory_order_relaxed);
+    if (g == 0) {
+      int per_cu = 0, cus = 0, dev = 0;
+      e = hipGetDevice(&dev);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), S::T, lds);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      g = (per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
+      resident.store(g, std::memory_order_relaxed);
+    }
+    uint64_t grid = job.n < (uint64_t)g ? job.n : (uint64_t)g;
+    FusedJob jb = job;
+    if (jb.ring) {  // each workgroup cycles through slots of its own: at most one per slot
+      if (!jb.dec_out) return hipErrorInvalidValue;
+      if (grid > jb.ring) grid = jb.ring;
+    }
+    if (!jb.cursor) return hipErrorInvalidValue;
+    e = launch_fill_u32(jb.cursor, kXcds, 0u, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cached_fused<LOGN, LOGR, RC, BRIGHT, DECRYPT, MISSES>), dim3((uint32_t)grid), dim3(S::T), lds,
+                       st, jb, c->d_lc, c->dev);
+    return hipGetLastError();
+  }
+  // misses: false when the job's cache holds every value (no pixel is encrypted in full)
+  static hipError_t fused(const ckks_ctx *c, const FusedJob &job, bool misses, hipStream_t st) {
+    if (job.n == 0) return hipSuccess;
+    const bool bright = job.seg_b != nullptr, dec = job.dec_out != nullptr;
+    if (!misses) {
+      if (!job.counters) return hipErrorInvalidValue;
+      if (bright) return dec ? fused_as<true, true, false>(c, job, st) : fused_as<true, false, false>(c, job, st);
+      return dec ? fused_as<false, true, false>(c, job, st) : fused_as<false, false, false>(c, job, st);
+    }
+    if (bright) return dec ? fused_as<true, true, true>(c, job, st) : fused_as<true, false, true>(c, job, st);
+    return dec ? fused_as<false, true, true>(c, job, st) : fused_as<false, false, true>(c, job, st);
   }
   static hipError_t keygen(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {
     hipError_t e = set_lds<LOGN, LOGR, k_keygen<LOGN, LOGR, RC>>();
@@ -477,19 +544,20 @@ struct Launch {
   }
   template <int LIMBS>
   static hipError_t decrypt_as(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale,
-                               double *out, hipStream_t st) {
+                               double *out, hipStream_t st, uint64_t max_grid) {
     hipError_t e = set_lds<LOGN, LOGR, k_decrypt<LOGN, LOGR, RC, LIMBS>>();
     if (e != hipSuccess) return e;
-    const uint64_t grid = n < (1u << 20) ? n : (1u << 20);
+    uint64_t grid = n < (1u << 20) ? n : (1u << 20);
+    if (max_grid && grid > max_grid) grid = max_grid;
     hipLaunchKernelGGL((k_decrypt<LOGN, LOGR, RC, LIMBS>), dim3((uint32_t)grid), dim3(S::T), S::lds_bytes, st, cts, n,
                        level, 1.0 / scale, out, c->d_lc, c->dev);
     return hipGetLastError();
   }
   static hipError_t decrypt(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale, double *out,
-                            int limbs, hipStream_t st) {
-    if (limbs == 2 && level >= 2) return decrypt_as<2>(c, cts, n, level, scale, out, st);
+                            int limbs, hipStream_t st, uint64_t max_grid) {
+    if (limbs == 2 && level >= 2) return decrypt_as<2>(c, cts, n, level, scale, out, st, max_grid);
     if (limbs != 1) return hipErrorInvalidValue;
-    return decrypt_as<1>(c, cts, n, level, scale, out, st);
+    return decrypt_as<1>(c, cts, n, level, scale, out, st, max_grid);
   }
 };
 
@@ -510,8 +578,9 @@ struct RingLaunch {
 
 }  // namespace ckks
 
-// Defines the per-ring-degree launcher entry points in one translation unit.
-#define CKKS_DEFINE_RING_LAUNCHERS(LOGN)                                                                            \
+// Define the per-ring-degree launcher entry points.  Each ring degree's kernels are spread
+// over three translation units (k_ntt_<LOGN>_{enc,mul,fused}.hip) so they compile in parallel.
+#define CKKS_DEFINE_RING_ENC(LOGN)                                                                                  \
   namespace ckks {                                                                                                  \
   hipError_t launch_encrypt_##LOGN(const ckks_ctx *c, const EncJob &job, uint64_t grid, hipStream_t st) {           \
     return RingLaunch<LOGN>::pick(c, c->logr_enc, [&](auto L) { return decltype(L)::encrypt(c, job, grid, st); });  \
@@ -522,6 +591,16 @@ struct RingLaunch {
   hipError_t launch_keys_prepare_##LOGN(const ckks_ctx *c, hipStream_t st) {                                        \
     return RingLaunch<LOGN>::pick(c, c->logr_enc, [&](auto L) { return decltype(L)::prepare(c, st); });             \
   }                                                                                                                 \
+  hipError_t launch_decrypt_##LOGN(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale,     \
+                                   double *out, int limbs, hipStream_t st, uint64_t max_grid) {                     \
+    return RingLaunch<LOGN>::pick(c, c->logr_dec, [&](auto L) {                                                     \
+      return decltype(L)::decrypt(c, cts, n, level, scale, out, limbs, st, max_grid);                               \
+    });                                                                                                             \
+  }                                                                                                                 \
+  }
+
+#define CKKS_DEFINE_RING_MUL(LOGN)                                                                                  \
+  namespace ckks {                                                                                                  \
   hipError_t launch_relin_keygen_##LOGN(const ckks_ctx *c, uint64_t s0, uint64_t s1, hipStream_t st) {              \
     return RingLaunch<LOGN>::pick(c, c->logr_mul, [&](auto L) { return decltype(L)::relin_keygen(c, s0, s1, st); });   \
   }                                                                                                                 \
@@ -533,9 +612,12 @@ struct RingLaunch {
     return RingLaunch<LOGN>::pick(                                                                                  \
         c, c->logr_mul, [&](auto L) { return decltype(L)::mul(c, a, b, out, n, level, scratch, st); });                \
   }                                                                                                                 \
-  hipError_t launch_decrypt_##LOGN(const ckks_ctx *c, const uint64_t *cts, uint64_t n, int level, double scale,     \
-                                   double *out, int limbs, hipStream_t st) {                                        \
-    return RingLaunch<LOGN>::pick(                                                                                  \
-        c, c->logr_dec, [&](auto L) { return decltype(L)::decrypt(c, cts, n, level, scale, out, limbs, st); });     \
+  }
+
+#define CKKS_DEFINE_RING_FUSED(LOGN)                                                                                \
+  namespace ckks {                                                                                                  \
+  hipError_t launch_cached_fused_##LOGN(const ckks_ctx *c, const FusedJob &job, bool misses, hipStream_t st) {     \
+    return RingLaunch<LOGN>::pick(c, misses ? c->logr_enc : c->logr_dec,                                            \
+                                  [&](auto L) { return decltype(L)::fused(c, job, misses, st); });                  \
   }                                                                                                                 \
   }

@@ -121,7 +121,7 @@ extern "C" int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const
     if (nbuf == 2 && t >= 2) e = hipStreamWaitEvent(E, ev_flt(b), 0);  // filter of tile t-2 has read enc[b]
     if (e != hipSuccess) break;
     if (cache) {
-      e = encrypt_cached_ws(ctx, cache, d_px + px0, n_in, seed[0], seed[1], first_index + px0, enc[b], ws, E);
+      e = encrypt_cached_ws(ctx, cache, d_px + px0, n_in, seed[0], seed[1], first_index + px0, enc[b], ws, E, true);
     } else {
       EncJob job;
       job.px = d_px + px0;
