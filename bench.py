@@ -30,27 +30,108 @@ ENC_SOURCES = ["paper_2409_03568_amd/csrc/" + f for f in
 COUNTERS_MD = os.path.join(ROOT, "profiles", "c2_step_hbm_counters.md")
 
 
-def measured_traffic(width):
-    """Bytes read + written per plain-encryption launch at this workload, from the counter
-    runs in profiles/, or None when they were taken at another NTT width or the kernel's
-    sources changed since."""
+def sources_sha256():
     import hashlib
 
-    try:
-        text = open(COUNTERS_MD).read()
-    except OSError:
-        return None
-    m = re.search(r"traffic k_encrypt_plain_c2 width=(\d+) read_bytes=(\d+) write_bytes=(\d+) .* "
-                  r"sources_sha256=([0-9a-f]+)", text)
-    if not m or int(m.group(1)) != width:
-        return None
     h = hashlib.sha256()
     for f in ENC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != m.group(4):
-        return None
-    return int(m.group(2)) + int(m.group(3))
+    return h.hexdigest()
+
+
+def measured_traffic(width):
+    """(bytes read + written per plain-encryption launch at this workload, source) from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in profiles/, or (None, why) when they
+    were taken at another NTT width or the kernel's sources changed since (the counters
+    cannot be read from inside this process)."""
+    try:
+        text = open(COUNTERS_MD).read()
+    except OSError:
+        return None, "no counter record"
+    m = re.search(r"traffic k_encrypt_plain_c2 width=(\d+) read_bytes=(\d+) write_bytes=(\d+) .* "
+                  r"sources_sha256=([0-9a-f]+)", text)
+    if not m:
+        return None, "no counter record"
+    if int(m.group(1)) != width:
+        return None, "counters recorded at width %s, this run uses %d" % (m.group(1), width)
+    if sources_sha256() != m.group(4):
+        return None, "kernel sources changed since the counters were recorded"
+    return int(m.group(2)) + int(m.group(3)), ("rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-calibrated) "
+                                               "from profiles/c2_step_hbm_counters.md, sources sha256 %s" % m.group(4)[:16])
+
+
+CONVENTION = ("FP64 VALU issue: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s, i.e. 78.6 TFLOP/s / 2 "
+              "with an FMA counted as one op; algorithmic ops = 8 per butterfly (6-op exact modular product + sum "
+              "+ difference) and 6 per pointwise modular product")
+
+
+def host_info():
+    """CPU model and logical CPU count of the host running the oracle."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def value_phase(ms, n, hits, S, ops_per_ct):
+    """Value-cached encryption against its roofline: each hit writes S bytes (its cache entry
+    and pool member are read from L2) and each miss is one plain encryption (FP64 VALU).  The
+    serial floor adds the two (hits at 8 TB/s, then misses at 39.3 T ops/s); the overlapped
+    floor is the larger of the two, what the misses running beside the hit gather can reach."""
+    if not ms:
+        return {"ms": 0.0}
+    misses = n - hits
+    t_hbm = hits * S / (PEAK_HBM_GBS * 1e9) * 1e3
+    t_alu = misses * ops_per_ct / PEAK_VALU_OPS * 1e3
+    return {"ms": round(ms, 3), "ct_per_s": round(n / (ms / 1e3)), "hits": hits, "misses": misses,
+            "GBps_write": round(n * S / (ms / 1e3) / 1e9, 1),
+            "roofline": {"floor_serial_ms": round(t_hbm + t_alu, 3), "floor_overlapped_ms": round(max(t_hbm, t_alu), 3),
+                         "frac_serial": round((t_hbm + t_alu) / ms, 4), "frac_overlapped": round(max(t_hbm, t_alu) / ms, 4),
+                         "hbm_part_ms": round(t_hbm, 3), "alu_part_ms": round(t_alu, 3)}}
+
+
+def c1_bench(P, W, runs):
+    """Config 1: 1024 pixels of a 32x32 uniform image at N = 4096, 3 x 36-bit primes, scale
+    2^30 -- plain encryption then decryption (the ciphertext output is 201 MB, about 25 us at
+    8 TB/s, so this size is bound by launch and ramp-up latency)."""
+    import torch
+
+    cfg = 1
+    c = W.CONFIGS[cfg]
+    img = W.config_image(cfg)
+    n = img.size
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale, device=0)
+    ctx.keygen(W.keygen_seed(cfg))
+    stream = torch.cuda.Stream()
+    px = torch.from_numpy(img.reshape(-1)).cuda()
+    ct = ctx.empty(n)
+    dec = torch.empty(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        ctx.encrypt_pixels(px, W.job_seed(cfg), out=ct, stream=stream)
+        ctx.decrypt_pixels(ct, out=dec, stream=stream)
+    stream.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(runs)]
+    for k in range(runs):
+        evs[k][0].record(stream)
+        ctx.encrypt_pixels(px, W.job_seed(cfg), out=ct, stream=stream)
+        evs[k][1].record(stream)
+        ctx.decrypt_pixels(ct, out=dec, stream=stream)
+        evs[k][2].record(stream)
+    stream.synchronize()
+    enc = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    de = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+    err = float(np.max(np.abs(dec.cpu().numpy() - img.reshape(-1))))
+    ctx.close()
+    return {"pixels": n, "encrypt_ms": round(enc, 4), "decrypt_ms": round(de, 4),
+            "ct_per_s": round(n / ((enc + de) / 1e3)), "encrypt_ct_per_s": round(n / (enc / 1e3)),
+            "max_abs_err": err}
 
 
 def parse():
@@ -58,7 +139,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=192, help="pixels in the oracle's timed sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=2048,
+                    help="pixels in the oracle's timed sample of config 2 (configs 1 and 5 scale with it; 0 = skip)")
+    ap.add_argument("--c1-runs", type=int, default=20, help="timed runs of config 1 (0 = skip)")
     ap.add_argument("--phases", default="plain,radix,value,filter,decrypt")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
@@ -72,6 +155,8 @@ def parse():
     ap.add_argument("--serving-jobs", type=int, default=200,
                     help="jobs per load point of the serving measurement (0 = skip it)")
     ap.add_argument("--serving-budget-gb", type=float, default=160.0, help="device bytes the server may hold")
+    ap.add_argument("--serving-tile-gb", type=float, default=0.0,
+                    help="cap on one job's row-tile buffers in the server (0 = whole images)")
     return ap.parse_args()
 
 
@@ -171,7 +256,10 @@ def matching_bench(P, W, runs):
 
 
 def cpu_baseline(cfg, img, sample):
-    """The oracle as it stands, on the host cores, over a bounded sample of the same work."""
+    """The oracle as it stands, on the host cores, over a bounded sample of the same work:
+    `sample` random pixels of the configuration's image through its steps (plain
+    encryption and decryption for config 1; plain, radix and value encryption, the k x k
+    filter and decryption for configs 2 and 5), caches prebuilt as on the GPU."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
@@ -181,47 +269,52 @@ def cpu_baseline(cfg, img, sample):
     e = c.extras
     o = O.Oracle(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
     o.keygen(W.keygen_seed(cfg))
-    H, Wd = img.shape
     px = img.reshape(-1)
     rng = np.random.default_rng(99)
-    idx = np.sort(rng.choice(px.size, size=sample, replace=False))
+    idx = np.sort(rng.choice(px.size, size=min(sample, px.size), replace=False))
     threads = O.num_threads()
     job, cseed = W.job_seed(cfg), W.cache_seed(cfg)
     pool = ThreadPoolExecutor(max_workers=threads)
-    # cache entries: built once, outside the per-pixel timing (as on the GPU)
-    rent = o.radix_entries(e["base"], e["digits"], cseed)
-    top = o.topk(o.histogram(px), e["topk"])
-    ventries = dict(zip(top, pool.map(lambda v: o.value_entry(v, cseed), top)))
-    pool_cts = np.stack(list(pool.map(lambda u: o.pool_entry(u, cseed), range(e["pool"]))))
+    full = "base" in e
+    if full:  # cache entries: built once, outside the per-pixel timing (as on the GPU)
+        rent = o.radix_entries(e["base"], e["digits"], cseed)
+        top = o.topk(o.histogram(px), e["topk"])
+        ventries = dict(zip(top, pool.map(lambda v: o.value_entry(v, cseed), top)))
+        pool_cts = np.stack(list(pool.map(lambda u: o.pool_entry(u, cseed), range(e["pool"]))))
     t = {}
     t0 = time.perf_counter()
     plain = np.stack(list(pool.map(lambda i: o.encrypt(int(px[i]), job, int(i)), idx)))
     t["plain"] = time.perf_counter() - t0
+    dec_cts, dec_level = plain, c.num_primes
+    if full:
+        t0 = time.perf_counter()
+        list(pool.map(lambda i: o.radix_encrypt(rent, e["base"], e["digits"], int(px[i]), job, int(i)), idx))
+        t["radix"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        list(pool.map(lambda i: o.value_encrypt(ventries.get(int(px[i])), pool_cts, e["pool"], int(px[i]), job,
+                                                int(i)), idx))
+        t["value"] = time.perf_counter() - t0
+        # filter: the oracle sums the k x k ciphertexts around each sampled pixel (taken from
+        # the sampled plain ciphertexts, which are of the same size), multiplies and rescales
+        k = e["k"]
+        patch = np.stack([plain[j % len(plain)] for j in range(k * k)])
+        t0 = time.perf_counter()
+        flt = list(pool.map(lambda i: o.mean_filter_pixel(patch, k, k, k, k // 2, k // 2)[0], idx))
+        t["filter"] = time.perf_counter() - t0
+        dec_cts, dec_level = flt, c.num_primes - 1
     t0 = time.perf_counter()
-    list(pool.map(lambda i: o.radix_encrypt(rent, e["base"], e["digits"], int(px[i]), job, int(i)), idx))
-    t["radix"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    list(pool.map(lambda i: o.value_encrypt(ventries.get(int(px[i])), pool_cts, e["pool"], int(px[i]), job, int(i)),
-                  idx))
-    t["value"] = time.perf_counter() - t0
-    # filter: the oracle sums the k x k ciphertexts around each sampled pixel (taken from
-    # the sampled plain ciphertexts, which are of the same size), multiplies and rescales
-    k = e["k"]
-    patch = np.stack([plain[j % len(plain)] for j in range(k * k)])
-    t0 = time.perf_counter()
-    list(pool.map(lambda i: o.mean_filter_pixel(patch, k, k, k, k // 2, k // 2), idx))
-    t["filter"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    list(pool.map(lambda j: o.decrypt(plain[j]), range(len(idx))))
+    list(pool.map(lambda j: o.decrypt(dec_cts[j], level=dec_level), range(len(idx))))
     t["decrypt"] = time.perf_counter() - t0
     total = sum(t.values())
+    steps = "plain, radix and value encryption, the %dx%d filter and decryption" % (e["k"], e["k"]) if full else \
+        "plain encryption and decryption"
     return {
-        "value": sample / total,
+        "value": len(idx) / total,
         "unit": "pixel-ciphertexts/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "%d random pixels of the same image through plain, radix and value encryption, the 3x3 filter "
-                  "and decryption (%d host threads, caches prebuilt)" % (sample, threads),
+        "sample": "%d random pixels of the config-%d image through %s (%d host threads, caches prebuilt; %.1f s)"
+                  % (len(idx), cfg, steps, threads, total),
         "phase_s": {k2: round(v, 3) for k2, v in t.items()},
     }
 
@@ -263,6 +356,7 @@ def batched_bench(P, W, runs):
     S = ctx.ct_bytes()
     res = {"images": len(imgs), "ciphertexts": int(n), "ms": round(ms, 2), "ct_per_s": round(n / (ms / 1e3)),
            "ciphertext_TB_per_run": round(n * S / 1e12, 3), "GBps_write": round(n * S / (ms / 1e3) / 1e9, 1),
+           "frac_of_8TBps": round(n * S / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
            "ring_cts": 65536, "graph": True, "max_abs_err": err,
            "autotune": {"encrypt_width": tune["encrypt_width"], "decrypt_width": tune["decrypt_width"],
                         "encrypt_ms": {str(k): round(v, 3) for k, v in tune["encrypt_ms"].items()},
@@ -328,7 +422,7 @@ def pipeline_bench(P, W, runs):
     return res
 
 
-def serving_bench(P, W, n_jobs, budget_gb):
+def serving_bench(P, W, n_jobs, budget_gb, tile_gb):
     """Serving workload: Poisson arrivals of encrypt (full value cache) -> 3x3 mean filter ->
     decrypt jobs on N=8192 / 4x50-bit; closed-loop saturation first, then open-loop
     arrivals at 0.5, 0.8 and 0.95 of it; latency = host clock from submission to the
@@ -345,9 +439,11 @@ def serving_bench(P, W, n_jobs, budget_gb):
     gaps, imgs = W.serving_jobs(e["seed"], n_jobs, e["lo"], e["hi"])
     px_total = int(sum(im.size for im in imgs))
     budget = int(budget_gb * 1e9)
-    max_job = max(P.job_bytes(ctx, *im.shape, e["k"]) for im in imgs)
+    tile_bytes = int(tile_gb * 1e9)
+    max_job = max(P.job_bytes(ctx, *im.shape, e["k"], cache, tile_bytes) for im in imgs)
+    max_job_whole = max(P.job_bytes(ctx, *im.shape, e["k"], cache) for im in imgs)
     srv = P.Server(ctx, budget, max_inflight=8, filter_k=e["k"], cache=cache,
-                   max_job_pixels=max(im.size for im in imgs))
+                   max_job_pixels=max(im.size for im in imgs), tile_bytes=tile_bytes)
 
     def run(arrivals):
         t0 = time.perf_counter()
@@ -371,8 +467,11 @@ def serving_bench(P, W, n_jobs, budget_gb):
     run(None)  # warm-up (pool allocations, pinned staging)
     wall, lat = run(None)
     sat_qps = len(imgs) / wall
+    sizes = np.array([im.size for im in imgs], dtype=np.float64)
     out = {"jobs_per_point": len(imgs), "pixels_per_job_mean": round(px_total / len(imgs), 1),
-           "max_job_GB": round(max_job / 1e9, 2), "budget_GB": round(budget / 1e9, 1), "slots": 8,
+           "job_pixels_p99_over_p50": round(float(np.percentile(sizes, 99) / np.percentile(sizes, 50)), 2),
+           "max_job_GB": round(max_job / 1e9, 2), "max_job_GB_untiled": round(max_job_whole / 1e9, 2),
+           "tile_GB": tile_gb, "budget_GB": round(budget / 1e9, 1), "slots": 8,
            "closed_loop": {"qps": round(sat_qps, 2), "px_per_s": round(px_total / wall),
                            "p50_ms": round(float(np.percentile(lat, 50)), 2),
                            "p99_ms": round(float(np.percentile(lat, 99)), 2)},
@@ -495,12 +594,13 @@ def main():
         achieved = ops / t_plain / 1e12
         peak = PEAK_VALU_OPS / 1e12
         width = ctx.ntt_width()
+        traffic, traffic_src = measured_traffic(width)
         roofline = {"bound": "alu",
                     "kernel": "k_encrypt<13, %d, 1, 0, false> (fused plain encryption, %d values per thread)"
                               % (width.bit_length() - 1, width),
                     "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TVALUop/s (FP64)",
                     "frac": round(achieved / peak, 4),
-                    "traffic": measured_traffic(width)}
+                    "traffic": traffic, "traffic_source": traffic_src, "convention": CONVENTION}
     # the HBM-bound kernels against the 8 TB/s peak (algorithmic bytes: radix and value
     # encryption write S per pixel, the filter reads S and writes S (L-1)/L per pixel)
     hbm = {}
@@ -518,8 +618,7 @@ def main():
         "plain": {"ms": round(phase_ms["plain"], 3), "ct_per_s": round(n / (phase_ms["plain"] / 1e3)) if phase_ms["plain"] else None},
         "radix": {"ms": round(phase_ms["radix"], 3), "ct_per_s": round(n / (phase_ms["radix"] / 1e3)) if phase_ms["radix"] else None,
                   "GBps_write": gbs(n * S, phase_ms["radix"])},
-        "value": {"ms": round(phase_ms["value"], 3), "ct_per_s": round(n / (phase_ms["value"] / 1e3)) if phase_ms["value"] else None,
-                  "hits": hits, "GBps_alg": gbs(n * S + hits * 2 * S, phase_ms["value"])},
+        "value": value_phase(phase_ms["value"], n, hits, S, ntt_ops_per_ct(c.log_n, c.num_primes)),
         "filter": {"ms": round(phase_ms["filter"], 3), "GBps_alg": gbs(n * S * (1 + (c.num_primes - 1) / c.num_primes),
                                                                         phase_ms["filter"])},
         "decrypt": {"ms": round(phase_ms["decrypt"], 3), "ct_per_s": round(n / (phase_ms["decrypt"] / 1e3)) if phase_ms["decrypt"] else None},
@@ -552,6 +651,8 @@ def main():
     ctx.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if args.c1_runs > 0:
+        out["c1"] = c1_bench(P, W, args.c1_runs)
     if args.batched_runs > 0:
         out["batched"] = batched_bench(P, W, args.batched_runs)
     if args.pipeline_runs > 0:
@@ -559,9 +660,13 @@ def main():
     if args.matching_runs > 0:
         out["matching"] = matching_bench(P, W, args.matching_runs)
     if args.serving_jobs > 0:
-        out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb)
+        out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb, args.serving_tile_gb)
     if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(cfg, img, args.cpu_sample)
+        cb = cpu_baseline(cfg, img, args.cpu_sample)
+        cb.update(host_info())
+        cb["per_config"] = {"c1": cpu_baseline(1, W.config_image(1), min(args.cpu_sample, 1024)),
+                            "c5": cpu_baseline(5, W.config_image(5), max(1, args.cpu_sample // 2))}
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 

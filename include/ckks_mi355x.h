@@ -58,6 +58,7 @@ extern "C" {
 #define CKKS_ECACHE (-7)        /* cache kind / descriptor mismatch, or pixel not representable */
 #define CKKS_EUNSUPPORTED (-8)  /* parameter outside what the kernels implement */
 #define CKKS_ESTATE (-9)        /* keys not generated or imported yet, or replaced since */
+#define CKKS_ECANCELED (-10)    /* a server job was cancelled before it was admitted */
 #define CKKS_PENDING 1          /* ckks_stream_status: work is still running (not an error) */
 
 typedef struct ckks_ctx ckks_ctx;
@@ -431,12 +432,14 @@ int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
  * `max_inflight` slots (each a HIP stream of its own) is free and a contiguous range of
  * the job's device bytes is free in the server's arena (one device allocation of
  * `hbm_budget_bytes` made at creation).  Admitted jobs run concurrently on their streams.
- * Job bytes = align(n) + n*S(L) + n*S(L-1) + align(8n) for n = H*W pixels and
- * S(l) = ckks_ct_bytes(ctx, l) (pixels, ciphertexts, filtered ciphertexts, decrypted
- * values); cached encryption also takes its small per-pixel metadata (12 bytes per pixel)
- * from the context's scratch pool.  A job's results do not depend on which other jobs run
- * beside it: its ciphertexts are fixed by (job_seed, first_index) and every kernel's
- * result is independent of the launch that computes it.
+ * A job runs in row tiles (as ckks_image_pipeline with one stream): its device bytes
+ * (ckks_job_bytes) are its pixels, its decrypted values and the buffers of one tile --
+ * encrypted rows with k/2 halo rows, filtered rows, cache metadata -- with the tile height
+ * the largest whose buffers fit `tile_bytes` (0 = the whole image as one tile), so a large
+ * image does not hold most of the arena while smaller jobs wait.  A job's results do not
+ * depend on which other jobs run beside it, nor on the tiling: its ciphertexts are fixed by
+ * (job_seed, first_index), halo rows are encrypted again bit-identically, and every
+ * kernel's result is independent of the launch that computes it.
  */
 typedef struct ckks_server ckks_server;
 
@@ -446,6 +449,7 @@ typedef struct {
   uint32_t filter_k;          /* mean-filter window: 1, 3, 5, 7; 0 = no filter (decrypt the encryption) */
   const ckks_cache *cache;    /* cache for encryption, NULL = plain encryption; must outlive the server */
   uint64_t max_job_pixels;    /* pinned staging sized for this many pixels per slot at creation (0 = on demand) */
+  uint64_t tile_bytes;        /* cap on one job's tile buffers (0 = whole image) */
 } ckks_server_config;
 
 typedef struct {
@@ -462,6 +466,7 @@ typedef struct {
   uint64_t submitted, completed, failed, queued, inflight;
   uint64_t arena_bytes, inflight_bytes, peak_inflight_bytes;
   uint32_t peak_inflight_jobs, reserved;
+  uint64_t canceled;
 } ckks_server_stats;
 
 /* Creates a server and starts its dispatcher.  Needs keys on ctx; ctx (and cache) must
@@ -474,6 +479,22 @@ int ckks_server_create(ckks_ctx *ctx, const ckks_server_config *cfg, ckks_server
  * index first_index + t under job_seed.  ENOMEM_BUDGET if the job can never fit. */
 int ckks_server_submit(ckks_server *srv, const uint8_t *host_px, uint32_t H, uint32_t W, const uint64_t job_seed[2],
                        uint64_t first_index, double *host_out, uint64_t *job_id);
+
+/* Arena bytes a job of H x W pixels takes in a server with this cache, filter window and
+ * tile_bytes (0 for H*W = 0 or a NULL context). */
+uint64_t ckks_job_bytes(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t filter_k,
+                        uint64_t tile_bytes);
+
+/* Cancels a job that is still queued: it is never admitted, and ckks_server_poll returns
+ * it with status CKKS_ECANCELED.  CKKS_ESTATE if it has already been admitted (it then
+ * runs to completion), CKKS_EINVAL for an unknown id. */
+int ckks_server_cancel(ckks_server *srv, uint64_t job_id);
+
+/* Failure injection, for testing a client's failure handling: when the (still queued) job
+ * is admitted, none of its work is enqueued and it finishes with `status` (a negative
+ * CKKS_E* code), as if one of its steps had failed; the jobs beside it are unaffected.
+ * CKKS_ESTATE if the job is not queued. */
+int ckks_server_inject_failure(ckks_server *srv, uint64_t job_id, int32_t status);
 
 /* Returns up to `max` finished jobs (oldest first), waiting up to wait_ms milliseconds
  * (0 = do not wait, negative = until at least one is available or nothing is pending). */

@@ -21,8 +21,9 @@ CKKS_OK = 0
 CKKS_PENDING = 1
 ERRORS = {
     -1: "CKKS_EINVAL", -2: "CKKS_ENOMEM", -3: "CKKS_ENOMEM_BUDGET", -4: "CKKS_EDEVICE", -5: "CKKS_ELEVEL",
-    -6: "CKKS_ESCALE", -7: "CKKS_ECACHE", -8: "CKKS_EUNSUPPORTED", -9: "CKKS_ESTATE",
+    -6: "CKKS_ESCALE", -7: "CKKS_ECACHE", -8: "CKKS_EUNSUPPORTED", -9: "CKKS_ESTATE", -10: "CKKS_ECANCELED",
 }
+ERRORS_BY_NAME = {v: k for k, v in ERRORS.items()}
 CKKS_CACHE_RADIX, CKKS_CACHE_VALUE_TOPK, CKKS_CACHE_VALUE_FULL = 1, 2, 3
 
 
@@ -51,7 +52,7 @@ class ckks_cache_desc_t(C.Structure):
 
 class ckks_server_config_t(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("filter_k", C.c_uint32),
-                ("cache", C.c_void_p), ("max_job_pixels", C.c_uint64)]
+                ("cache", C.c_void_p), ("max_job_pixels", C.c_uint64), ("tile_bytes", C.c_uint64)]
 
 
 class ckks_job_result_t(C.Structure):
@@ -64,7 +65,7 @@ class ckks_server_stats_t(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
                 ("queued", C.c_uint64), ("inflight", C.c_uint64), ("arena_bytes", C.c_uint64),
                 ("inflight_bytes", C.c_uint64), ("peak_inflight_bytes", C.c_uint64),
-                ("peak_inflight_jobs", C.c_uint32), ("reserved", C.c_uint32)]
+                ("peak_inflight_jobs", C.c_uint32), ("reserved", C.c_uint32), ("canceled", C.c_uint64)]
 
 
 class ckks_tune_report_t(C.Structure):
@@ -147,6 +148,9 @@ _SIGS = {
     "ckks_server_poll": (C.c_int, [C.c_void_p, C.POINTER(ckks_job_result_t), C.c_uint32, C.POINTER(C.c_uint32),
                                    C.c_int32]),
     "ckks_server_drain": (C.c_int, [C.c_void_p]),
+    "ckks_server_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ckks_server_inject_failure": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32]),
+    "ckks_job_bytes": (C.c_uint64, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64]),
     "ckks_server_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ckks_server_stats_t)]),
     "ckks_server_destroy": (None, [C.c_void_p]),
 }
@@ -565,15 +569,11 @@ class BatchPlan:
             pass
 
 
-def job_bytes(ctx: Context, H: int, W: int, filter_k: int) -> int:
-    """Arena bytes a server job of H x W pixels takes (pixels, ciphertexts, filtered
-    ciphertexts if filter_k, decrypted values), as the server's admission counts them."""
-    n = H * W
-    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    b = al(n) + n * ctx.ct_bytes(ctx.L) + al(8 * n)
-    if filter_k:
-        b += n * ctx.ct_bytes(ctx.L - 1)
-    return b
+def job_bytes(ctx: Context, H: int, W: int, filter_k: int, cache: "Cache | None" = None, tile_bytes: int = 0) -> int:
+    """Arena bytes a server job of H x W pixels takes (ckks_job_bytes): pixels, decrypted
+    values and one row tile's buffers, as the server's admission counts them."""
+    return int(lib().ckks_job_bytes(ctx.handle, cache.handle if cache is not None else None, int(H), int(W),
+                                    int(filter_k), int(tile_bytes)))
 
 
 class Server:
@@ -582,19 +582,28 @@ class Server:
     `max_inflight` running at once, each on its own stream."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int, max_inflight: int = 4, filter_k: int = 3,
-                 cache: "Cache | None" = None, max_job_pixels: int = 0):
+                 cache: "Cache | None" = None, max_job_pixels: int = 0, tile_bytes: int = 0):
         cfg = ckks_server_config_t(int(hbm_budget_bytes), int(max_inflight), int(filter_k),
-                                   cache.handle if cache is not None else None, int(max_job_pixels))
+                                   cache.handle if cache is not None else None, int(max_job_pixels), int(tile_bytes))
         h = C.c_void_p()
         _check(lib().ckks_server_create(ctx.handle, C.byref(cfg), C.byref(h)))
         self.handle = h
         self.ctx = ctx
         self.cache = cache
         self.filter_k = int(filter_k)
+        self.tile_bytes = int(tile_bytes)
         self._outputs = {}  # job id -> (pixels copy owner, output array): kept alive until polled
 
     def job_bytes(self, H: int, W: int) -> int:
-        return job_bytes(self.ctx, H, W, self.filter_k)
+        return job_bytes(self.ctx, H, W, self.filter_k, self.cache, self.tile_bytes)
+
+    def cancel(self, job_id: int):
+        """Cancel a queued job (ckks_server_cancel); it is polled with status CKKS_ECANCELED."""
+        _check(lib().ckks_server_cancel(self.handle, int(job_id)))
+
+    def inject_failure(self, job_id: int, status: int = -4):
+        """Make a queued job fail when admitted (ckks_server_inject_failure), for failure tests."""
+        _check(lib().ckks_server_inject_failure(self.handle, int(job_id), int(status)))
 
     def submit(self, img, seed, first_index: int = 0) -> int:
         img = np.ascontiguousarray(img, dtype=np.uint8)

@@ -127,6 +127,16 @@ class Admission {
     return true;
   }
 
+  // Removes one queued job; false if it is not in the queue.
+  bool cancel(uint64_t id) {
+    for (auto it = queue_.begin(); it != queue_.end(); ++it)
+      if (it->id == id) {
+        queue_.erase(it);
+        return true;
+      }
+    return false;
+  }
+
   // Drops every job still queued (their ids are appended to out).
   template <class Out>
   void cancel_queued(Out &out) {

@@ -201,6 +201,18 @@ double encryption_terms(const ckks_cache *cache);
 // below q_0/2.  Internal pipelines whose inputs are pixels use it to decode one limb.
 bool limb0_decode_exact(const ckks_ctx *c, double value_bound, double terms, bool filtered);
 
+// Row tiles of an image job (pipeline.cpp): bytes of one tile's buffers (encrypted rows with
+// k/2 halo rows, filtered rows, cache metadata), the largest tile height within a byte
+// budget (0 = the whole image), and encrypt -> k x k filter (k = 0: none) -> decrypt of
+// the image tile by tile on one stream with those buffers at `mem`.
+uint64_t tile_ws_bytes(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t k,
+                       uint32_t tile_rows);
+uint32_t tile_rows_for(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t k,
+                       uint64_t budget);
+hipError_t run_tiles(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint32_t H, uint32_t W,
+                     uint64_t seed0, uint64_t seed1, uint64_t first_index, uint32_t k, uint32_t tile_rows,
+                     const uint64_t *K, double out_scale, int dec_limbs, double *d_out, void *mem, hipStream_t st);
+
 // Launchers (return a hipError_t; enqueue on `stream`).
 // misses = false: the cache holds every value (VALUE_FULL), so only hits occur; the kernel
 // is then compiled without the encryption path (decryption-sized LDS and registers) and

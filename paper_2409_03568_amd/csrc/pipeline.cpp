@@ -48,7 +48,87 @@ struct DeviceScope {
 
 uint64_t al(uint64_t x) { return (x + 255) / 256 * 256; }
 
+// Byte sizes of one tile's buffers: encrypted rows (with halos), filtered rows, cache metadata.
+struct TileSizes {
+  uint32_t rows = 0, cap_rows = 0;
+  uint64_t enc = 0, flt = 0, ws = 0;
+};
+
+TileSizes tile_sizes(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t k,
+                     uint32_t tile_rows) {
+  const uint32_t L = (uint32_t)ctx->prm.L, R = k / 2;
+  TileSizes t;
+  t.rows = tile_rows < H ? tile_rows : H;
+  t.cap_rows = t.rows + 2 * R < H ? t.rows + 2 * R : H;
+  t.enc = al((uint64_t)t.cap_rows * W * ckks_ct_bytes(ctx, L));
+  t.flt = k ? al((uint64_t)t.rows * W * ckks_ct_bytes(ctx, L - 1)) : 0;
+  t.ws = cache ? al(cached_ws_bytes(cache, (uint64_t)t.cap_rows * W)) : 0;
+  return t;
+}
+
 }  // namespace
+
+namespace ckks {
+
+uint64_t tile_ws_bytes(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t k,
+                       uint32_t tile_rows) {
+  const TileSizes t = tile_sizes(ctx, cache, H, W, k, tile_rows);
+  return t.enc + t.flt + t.ws;
+}
+
+uint32_t tile_rows_for(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t k,
+                       uint64_t budget) {
+  if (!budget) return H;
+  uint32_t lo = 1, hi = H;  // the largest row count whose buffers fit the budget (at least one row)
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (tile_ws_bytes(ctx, cache, H, W, k, mid) <= budget)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+hipError_t run_tiles(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint32_t H, uint32_t W,
+                     uint64_t seed0, uint64_t seed1, uint64_t first_index, uint32_t k, uint32_t tile_rows,
+                     const uint64_t *K, double out_scale, int dec_limbs, double *d_out, void *mem, hipStream_t st) {
+  const uint32_t L = (uint32_t)ctx->prm.L, R = k / 2;
+  const TileSizes ts = tile_sizes(ctx, cache, H, W, k, tile_rows);
+  uint8_t *m = static_cast<uint8_t *>(mem);
+  uint64_t *enc = reinterpret_cast<uint64_t *>(m), *flt = reinterpret_cast<uint64_t *>(m + ts.enc);
+  void *ws = m + ts.enc + ts.flt;
+  hipError_t e = hipSuccess;
+  for (uint32_t r0 = 0; r0 < H && e == hipSuccess; r0 += ts.rows) {
+    const uint32_t r1 = r0 + ts.rows < H ? r0 + ts.rows : H;
+    const uint32_t s0 = r0 >= R ? r0 - R : 0, s1 = r1 + R < H ? r1 + R : H;
+    const uint64_t n_in = (uint64_t)(s1 - s0) * W, px0 = (uint64_t)s0 * W;
+    if (cache) {
+      e = encrypt_cached_ws(ctx, cache, d_px + px0, n_in, seed0, seed1, first_index + px0, enc, ws, st, true);
+    } else {
+      EncJob job;
+      job.px = d_px + px0;
+      job.n = n_in;
+      job.first_index = first_index + px0;
+      job.seed0 = seed0;
+      job.seed1 = seed1;
+      job.out = enc;
+      e = launch_encrypt(ctx, job, n_in < (1u << 24) ? n_in : (1u << 24), st);
+    }
+    if (e != hipSuccess) break;
+    if (k) {
+      e = launch_mean_filter(ctx, enc, flt, s1 - s0, W, r0 - s0, r1 - s0, k, (int)L, K, st);
+      if (e == hipSuccess)
+        e = launch_decrypt(ctx, flt, (uint64_t)(r1 - r0) * W, (int)L - 1, out_scale, d_out + (uint64_t)r0 * W,
+                           L - 1 >= 2 ? dec_limbs : 1, st);
+    } else {
+      e = launch_decrypt(ctx, enc, n_in, (int)L, out_scale, d_out + (uint64_t)r0 * W, L >= 2 ? dec_limbs : 1, st);
+    }
+  }
+  return e;
+}
+
+}  // namespace ckks
 
 extern "C" int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint32_t H,
                                    uint32_t W, const uint64_t seed[2], uint64_t first_index,
@@ -93,6 +173,16 @@ extern "C" int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const
     D = ctx->pipe[2];
   }
   uint8_t *mem = nullptr;
+  if (nbuf == 1) {  // one stream: the tiles one after another
+    const uint64_t total = tile_ws_bytes(ctx, cache, H, W, k, T);
+    if (hipMallocFromPoolAsync(reinterpret_cast<void **>(&mem), total, ctx->pool, user) != hipSuccess)
+      return api_fail(CKKS_ENOMEM, "pipeline buffers (%llu bytes)", (unsigned long long)total);
+    const hipError_t e1 = run_tiles(ctx, cache, d_px, H, W, seed[0], seed[1], first_index, k, T, K.data(), out_scale,
+                                    dec_limbs, d_out, mem, user);
+    (void)hipFreeAsync(mem, user);
+    if (e1 != hipSuccess) return api_fail(CKKS_EDEVICE, "image pipeline: %s", hipGetErrorString(e1));
+    return CKKS_OK;
+  }
   const uint64_t total = nbuf * (enc_bytes + flt_bytes) + ws_bytes;
   if (hipMallocFromPoolAsync(reinterpret_cast<void **>(&mem), total, ctx->pool, user) != hipSuccess)
     return api_fail(CKKS_ENOMEM, "pipeline buffers (%llu bytes)", (unsigned long long)total);

@@ -31,6 +31,7 @@ uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Job {
   uint64_t id = 0;
+  int forced_status = 0;  // failure injected by ckks_server_inject_failure (0 = none)
   uint32_t H = 0, W = 0;
   uint64_t n = 0;
   uint64_t seed[2] = {0, 0};
@@ -59,6 +60,8 @@ struct ckks_server {
   ckks_ctx *ctx = nullptr;
   uint64_t key_epoch = 0;  // keys the server was created under
   int dec_limbs = 1;       // limbs decoded by decryption (see limb0_decode_exact)
+  std::vector<uint64_t> K;  // the filter's multiplier rint(q_{L-1} / k^2) per limb
+  double out_scale = 0.0;   // scale of the decrypted values
   ckks_server_config cfg{};
   uint8_t *arena = nullptr;
   ckks::rt::Admission adm;
@@ -84,11 +87,17 @@ struct ckks_server {
 
 namespace {
 
-uint64_t job_bytes(const ckks_server *s, uint64_t n) {
-  const uint32_t L = (uint32_t)s->ctx->prm.L;
-  uint64_t b = align_up(n) + n * ckks_ct_bytes(s->ctx, L) + align_up(8 * n);
-  if (s->cfg.filter_k) b += n * ckks_ct_bytes(s->ctx, L - 1);
-  return b;
+// Arena bytes of a job: its pixels and decrypted values, and the buffers of one row tile
+// (tile_bytes caps those; 0 = the whole image in one tile).
+uint64_t job_bytes_of(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t k,
+                      uint64_t tile_bytes) {
+  const uint64_t n = (uint64_t)H * W;
+  const uint32_t rows = ckks::tile_rows_for(ctx, cache, H, W, k, tile_bytes);
+  return align_up(n) + align_up(8 * n) + ckks::tile_ws_bytes(ctx, cache, H, W, k, rows);
+}
+
+uint64_t job_bytes(const ckks_server *s, uint32_t H, uint32_t W) {
+  return job_bytes_of(s->ctx, s->cfg.cache, H, W, s->cfg.filter_k, s->cfg.tile_bytes);
 }
 
 hipError_t ensure_pinned(Slot &sl, uint64_t n) {
@@ -104,30 +113,24 @@ hipError_t ensure_pinned(Slot &sl, uint64_t n) {
   return e;
 }
 
-// Enqueues the whole job on the slot's stream; returns the status of the first failing step.
+// Enqueues the whole job on the slot's stream -- pixels in, then encrypt -> filter -> decrypt
+// tile by tile in the job's arena range, decrypted values out; returns the status of the
+// first failing step (or the injected failure, before any device work).
 int launch_job(ckks_server *s, Slot &sl) {
   const Job &j = sl.job;
+  if (j.forced_status) return j.forced_status;
   ckks_ctx *ctx = s->ctx;
-  const uint32_t L = (uint32_t)ctx->prm.L;
   if (ensure_pinned(sl, j.n) != hipSuccess) return CKKS_ENOMEM;
   memcpy(sl.pin_px, j.px.data(), j.n);
   uint8_t *base = s->arena + sl.offset;
   uint8_t *d_px = base;
-  uint64_t *d_ct = reinterpret_cast<uint64_t *>(base + align_up(j.n));
-  uint64_t *d_flt = d_ct + j.n * (ckks_ct_bytes(ctx, L) / 8);
-  double *d_out = reinterpret_cast<double *>(s->cfg.filter_k ? d_flt + j.n * (ckks_ct_bytes(ctx, L - 1) / 8) : d_flt);
-  void *st = sl.st;
+  double *d_out = reinterpret_cast<double *>(base + align_up(j.n));
+  void *tiles = base + align_up(j.n) + align_up(8 * j.n);
+  const uint32_t rows = ckks::tile_rows_for(ctx, s->cfg.cache, j.H, j.W, s->cfg.filter_k, s->cfg.tile_bytes);
   if (hipEventRecord(sl.ev0, sl.st) != hipSuccess) return CKKS_EDEVICE;
   if (hipMemcpyAsync(d_px, sl.pin_px, j.n, hipMemcpyHostToDevice, sl.st) != hipSuccess) return CKKS_EDEVICE;
-  ckks_ct_batch ct{d_ct, 0, 0, 0, 0.0};
-  int rc = s->cfg.cache ? ckks_encrypt_cached(ctx, s->cfg.cache, d_px, j.n, j.seed, j.first_index, &ct, st)
-                        : ckks_encrypt_pixels(ctx, d_px, j.n, j.seed, j.first_index, &ct, st);
-  if (rc) return rc;
-  ckks_ct_batch flt{d_flt, 0, 0, 0, 0.0};
-  if (s->cfg.filter_k && (rc = ckks_mean_filter(ctx, &ct, j.H, j.W, s->cfg.filter_k, &flt, st))) return rc;
-  const ckks_ct_batch &res = s->cfg.filter_k ? flt : ct;
-  if (ckks::launch_decrypt(ctx, res.data, res.count, (int)res.level, res.scale, d_out,
-                           res.level >= 2 ? s->dec_limbs : 1, sl.st) != hipSuccess)
+  if (ckks::run_tiles(ctx, s->cfg.cache, d_px, j.H, j.W, j.seed[0], j.seed[1], j.first_index, s->cfg.filter_k, rows,
+                      s->K.data(), s->out_scale, s->dec_limbs, d_out, tiles, sl.st) != hipSuccess)
     return CKKS_EDEVICE;
   if (hipMemcpyAsync(sl.pin_out, d_out, j.n * sizeof(double), hipMemcpyDeviceToHost, sl.st) != hipSuccess)
     return CKKS_EDEVICE;
@@ -239,6 +242,16 @@ int ckks_server_create(ckks_ctx *ctx, const ckks_server_config *cfg, ckks_server
   s->key_epoch = ctx->key_epoch;
   s->dec_limbs = ckks::limb0_decode_exact(ctx, 255.0, ckks::encryption_terms(cfg->cache), cfg->filter_k != 0) ? 1 : 2;
   s->cfg = *cfg;
+  s->out_scale = ctx->scale;
+  if (k) {
+    double s1 = 0;
+    const int rc = ckks::filter_multiplier(ctx, (uint32_t)ctx->prm.L, ctx->scale, k, s->K, &s1);
+    if (rc) {
+      delete s;
+      return rc;
+    }
+    s->out_scale = s1 / (double)ctx->prm.q[ctx->prm.L - 1];
+  }
   s->t0 = Clock::now();
   int dev_prev = -1;
   (void)hipGetDevice(&dev_prev);
@@ -268,7 +281,7 @@ int ckks_server_submit(ckks_server *s, const uint8_t *host_px, uint32_t H, uint3
     return ckks::api_fail(CKKS_ESTATE, "the keys were replaced after the server was created");
   const uint64_t n = (uint64_t)H * W;
   if (n == 0 || n > 0xFFFFFFFFull) return ckks::api_fail(CKKS_EINVAL, "H*W must be in 1..2^32-1");
-  const uint64_t bytes = job_bytes(s, n);
+  const uint64_t bytes = job_bytes(s, H, W);
   if (!s->adm.fits_ever(bytes))
     return ckks::api_fail(CKKS_ENOMEM_BUDGET, "job needs %llu bytes, budget is %llu", (unsigned long long)bytes,
                           (unsigned long long)s->adm.arena().capacity());
@@ -311,6 +324,47 @@ int ckks_server_poll(ckks_server *s, ckks_job_result *out, uint32_t max, uint32_
   }
   *n_out = k;
   return CKKS_OK;
+}
+
+int ckks_server_cancel(ckks_server *s, uint64_t job_id) {
+  if (!s) return ckks::api_fail(CKKS_EINVAL, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->queued.find(job_id);
+    if (it == s->queued.end() || !s->adm.cancel(job_id)) {
+      if (job_id == 0 || job_id >= s->next_id) return ckks::api_fail(CKKS_EINVAL, "no job %llu", (unsigned long long)job_id);
+      return ckks::api_fail(CKKS_ESTATE, "job %llu has already been admitted", (unsigned long long)job_id);
+    }
+    ckks_job_result r{};
+    r.job_id = job_id;
+    r.status = CKKS_ECANCELED;
+    r.height = it->second.H;
+    r.width = it->second.W;
+    r.t_submit_us = it->second.t_submit;
+    r.t_done_us = s->now_us();
+    s->results.push_back(r);
+    s->queued.erase(it);
+    s->st.canceled++;
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_one();
+  return CKKS_OK;
+}
+
+int ckks_server_inject_failure(ckks_server *s, uint64_t job_id, int32_t status) {
+  if (!s) return ckks::api_fail(CKKS_EINVAL, "server is NULL");
+  if (status >= 0) return ckks::api_fail(CKKS_EINVAL, "an injected status must be a CKKS_E* code");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->queued.find(job_id);
+  if (it == s->queued.end()) return ckks::api_fail(CKKS_ESTATE, "job %llu is not queued", (unsigned long long)job_id);
+  it->second.forced_status = status;
+  return CKKS_OK;
+}
+
+uint64_t ckks_job_bytes(const ckks_ctx *ctx, const ckks_cache *cache, uint32_t H, uint32_t W, uint32_t filter_k,
+                        uint64_t tile_bytes) {
+  if (!ctx || (uint64_t)H * W == 0) return 0;
+  return job_bytes_of(ctx, cache, H, W, filter_k, tile_bytes);
 }
 
 int ckks_server_drain(ckks_server *s) {

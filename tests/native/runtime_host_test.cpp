@@ -87,11 +87,24 @@ static void admission_order() {
   CHECK(adm.finish(out[0].offset));  // everything free: job 4 then job 5
   CHECK(adm.admit(out) == 2 && out[3].id == 4 && out[4].id == 5);
   CHECK(!adm.finish(12345));
+  // cancelling one queued job removes it alone, keeping the others' order
+  adm.push(7, 256);
+  adm.push(8, 256);
+  adm.push(9, 256);
+  CHECK(adm.cancel(8) && !adm.cancel(8) && !adm.cancel(12345) && adm.queued() == 3 - 1);
+  CHECK(adm.finish(out[3].offset));
+  std::vector<Admitted> more;
+  CHECK(adm.admit(more) == 1 && more[0].id == 7);
+  CHECK(adm.finish(more[0].offset));
+  CHECK(adm.admit(more) == 1 && more[1].id == 9);
+  CHECK(adm.finish(more[1].offset));
+  CHECK(adm.admit(more) == 0);
+  out[3] = {0, 0};
   std::vector<uint64_t> dropped;
   adm.push(6, 256);
   adm.cancel_queued(dropped);
   CHECK(dropped.size() == 1 && dropped[0] == 6 && adm.queued() == 0);
-  CHECK(adm.finish(out[3].offset) && adm.finish(out[4].offset));
+  CHECK(adm.finish(out[4].offset));
   CHECK(adm.arena().used() == 0 && adm.free_slots() == 2);
 }
 

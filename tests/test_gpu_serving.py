@@ -71,7 +71,7 @@ def test_alone_vs_mix(env, use_cache, k):
     gaps, imgs = _jobs(W, 14, seed=40 + k)
     seeds = [(4, 1000 + i) for i in range(len(imgs))]
     # the mix: arrivals 0.3 ms apart on average, at most 4 jobs on the device
-    budget = 3 * max(P.job_bytes(ctx, *im.shape, k) for im in imgs)
+    budget = 3 * max(P.job_bytes(ctx, *im.shape, k, cache) for im in imgs)
     srv = P.Server(ctx, budget, max_inflight=4, filter_k=k, cache=cache)
     ids = {}
     for g, im, sd in zip(gaps, imgs, seeds):
@@ -110,7 +110,7 @@ def test_admission_budget(env):
     srv.close()
     # budget of one largest job: jobs run one at a time although two slots exist
     gaps, imgs = _jobs(W, 8, seed=77, lo=8, hi=24)
-    budget = max(P.job_bytes(ctx, *im.shape, 3) for im in imgs)
+    budget = max(P.job_bytes(ctx, *im.shape, 3, cache) for im in imgs)
     srv = P.Server(ctx, budget, max_inflight=2, filter_k=3, cache=cache)
     for i, im in enumerate(imgs):
         srv.submit(im, (4, 2000 + i))
@@ -131,7 +131,7 @@ def test_jobs_overlap(env):
     P, W, ctx, cache = env
     _say("[gpu] serving overlap")
     imgs = [W.zipf_image(90 + i, 64, 64) for i in range(6)]
-    budget = 3 * P.job_bytes(ctx, 64, 64, 3)
+    budget = 3 * P.job_bytes(ctx, 64, 64, 3, cache)
     srv = P.Server(ctx, budget, max_inflight=4, filter_k=3, cache=cache)
     for i, im in enumerate(imgs):
         srv.submit(im, (4, 3000 + i))
@@ -157,7 +157,7 @@ def test_mix_sampled_against_oracle(env, oracle_mod):
     _say("[gpu] serving mix vs oracle")
     gaps, imgs = _jobs(W, 6, seed=91, lo=5, hi=18)
     k = 3
-    budget = 2 * max(P.job_bytes(ctx, *im.shape, k) for im in imgs)
+    budget = 2 * max(P.job_bytes(ctx, *im.shape, k, cache) for im in imgs)
     srv = P.Server(ctx, budget, max_inflight=3, filter_k=k, cache=cache)
     ids = {}
     for i, im in enumerate(imgs):
@@ -182,3 +182,86 @@ def test_mix_sampled_against_oracle(env, oracle_mod):
             ref, sc = o.mean_filter_pixel(np.stack(win), k, k, k, R, R)
             val = o.decrypt(ref, level=2, scale=sc)
             assert abs(res[i]["pixels"][y, x] - val) < 1e-9, (i, y, x)
+
+
+def _alone(P, ctx, cache, img, seed, k, first_index=0, tile_bytes=0):
+    srv = P.Server(ctx, 2 * P.job_bytes(ctx, *img.shape, k, cache, tile_bytes), max_inflight=1, filter_k=k,
+                   cache=cache, tile_bytes=tile_bytes)
+    srv.submit(img, seed, first_index)
+    srv.drain()
+    (r,) = srv.poll(4)
+    srv.close()
+    assert r["status"] == 0
+    return r["pixels"]
+
+
+def test_tiled_jobs_bound_the_footprint(env):
+    # row tiles cap a job's device bytes; the result is the untiled one, bit for bit
+    P, W, ctx, cache = env
+    _say("[gpu] serving tiled jobs")
+    img = W.zipf_image(93, 70, 45)
+    k = 5
+    whole = P.job_bytes(ctx, 70, 45, k, cache)
+    cap = whole // 6
+    tiled = P.job_bytes(ctx, 70, 45, k, cache, cap)
+    assert tiled < whole and tiled <= cap + 70 * 45 * 9 + 4096
+    ref = _alone(P, ctx, cache, img, (4, 7000), k)
+    got = _alone(P, ctx, cache, img, (4, 7000), k, tile_bytes=cap)
+    assert np.array_equal(got, ref)
+    one_row = _alone(P, ctx, cache, img, (4, 7000), k, tile_bytes=1)  # at least one row per tile
+    assert np.array_equal(one_row, ref)
+    assert np.max(np.abs(ref - _box(img, k))) < 2e-3
+
+
+def test_cancel_before_admission(env):
+    P, W, ctx, cache = env
+    _say("[gpu] serving cancellation")
+    big = W.zipf_image(94, 256, 256)
+    small = [W.zipf_image(95 + i, 24, 20) for i in range(3)]
+    srv = P.Server(ctx, 4 * P.job_bytes(ctx, 256, 256, 3, cache), max_inflight=1, filter_k=3, cache=cache)
+    ja = srv.submit(big, (4, 8000))
+    ids = [srv.submit(im, (4, 8001 + i)) for i, im in enumerate(small)]
+    srv.cancel(ids[1])  # queued behind the running large job
+    with pytest.raises(P.CkksError) as e:
+        srv.cancel(ids[1])  # no longer queued
+    assert e.value.name == "CKKS_ESTATE"
+    with pytest.raises(P.CkksError) as e:
+        srv.cancel(10**9)
+    assert e.value.name == "CKKS_EINVAL"
+    srv.drain()
+    res = {r["id"]: r for r in srv.poll(16)}
+    st = srv.stats()
+    srv.close()
+    assert res[ids[1]]["status"] == P.ERRORS_BY_NAME["CKKS_ECANCELED"]
+    assert st["canceled"] == 1 and st["completed"] == 3
+    assert res[ja]["status"] == 0
+    for i in (0, 2):
+        assert res[ids[i]]["status"] == 0
+        assert np.array_equal(res[ids[i]]["pixels"], _alone(P, ctx, cache, small[i], (4, 8001 + i), 3))
+
+
+def test_failure_mid_mix_leaves_others_unchanged(env):
+    P, W, ctx, cache = env
+    _say("[gpu] serving failure injection")
+    bigs = [W.zipf_image(110 + i, 200, 200) for i in range(2)]
+    smalls = [W.zipf_image(120 + i, 30, 26) for i in range(4)]
+    srv = P.Server(ctx, 6 * P.job_bytes(ctx, 200, 200, 3, cache), max_inflight=2, filter_k=3, cache=cache)
+    ids = [srv.submit(im, (4, 9000 + i)) for i, im in enumerate(bigs)]
+    ids += [srv.submit(im, (4, 9100 + i)) for i, im in enumerate(smalls)]
+    srv.inject_failure(ids[3], -4)  # queued behind the two large jobs
+    with pytest.raises(P.CkksError):  # only a CKKS_E* code can be injected
+        srv.inject_failure(ids[4], 0)
+    with pytest.raises(P.CkksError) as e:  # an invalid job inside the mix is refused at submission
+        srv.submit(np.zeros((0, 5), np.uint8), (4, 1))
+    assert e.value.name == "CKKS_EINVAL"
+    srv.drain()
+    res = {r["id"]: r for r in srv.poll(16)}
+    st = srv.stats()
+    srv.close()
+    assert res[ids[3]]["status"] == -4 and st["failed"] == 1 and st["completed"] == 5
+    for j, (im, sd) in enumerate([(bigs[0], (4, 9000)), (bigs[1], (4, 9001))] +
+                                 [(smalls[i], (4, 9100 + i)) for i in range(4)]):
+        if j == 3:
+            continue
+        assert res[ids[j]]["status"] == 0
+        assert np.array_equal(res[ids[j]]["pixels"], _alone(P, ctx, cache, im, sd, 3)), j
