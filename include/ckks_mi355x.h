@@ -59,6 +59,7 @@ extern "C" {
 #define CKKS_EUNSUPPORTED (-8)  /* parameter outside what the kernels implement */
 #define CKKS_ESTATE (-9)        /* keys not generated or imported yet, or replaced since */
 #define CKKS_ECANCELED (-10)    /* a server job was cancelled before it was admitted */
+#define CKKS_EIO (-11)          /* a file could not be read or written */
 #define CKKS_PENDING 1          /* ckks_stream_status: work is still running (not an error) */
 
 typedef struct ckks_ctx ckks_ctx;
@@ -332,18 +333,45 @@ int ckks_stream_status(ckks_ctx *ctx, void *stream);
  * supported register blocking (8, 16 or 32 values per thread) on trial_cts synthetic
  * ciphertexts, and, once ckks_relin_keygen has run, the relinearized product
  * (Sec. 2.2.3) of trial_cts pairs; keeps the fastest width for each kernel on this
- * context and reports the timings.  The choice changes speed only, never results.
- * Enqueues on the null stream and synchronizes; allocates and frees its own scratch
- * buffers.
+ * context.  Then times the launch shapes of the HBM-bound kernels: the row-wise
+ * kernels (ciphertext addition, Sec. 2.2.3, standing for every row-wise kernel:
+ * subtraction, constants, rescaling, radix gather) at 0 (one workgroup per row), 2, 4,
+ * 8 and 16 workgroups per compute unit, and the value-cache gather (Sec. 3.2) at 2, 4,
+ * 8, 16 and 32, on trial_cts synthetic ciphertexts; keeps the fastest of each.  Reports
+ * every timing.  The choices change speed only, never results.  Enqueues on the null
+ * stream and synchronizes; allocates and frees its own scratch buffers.
  */
 typedef struct {
   uint32_t encrypt_width, decrypt_width;  /* chosen values per thread */
   uint32_t trial_cts, mul_width;          /* mul_width 0: product not timed (no keys) */
   double encrypt_ms[3], decrypt_ms[3];    /* best of 3 runs: [0] 8, [1] 16, [2] 32 values per thread */
   double mul_ms[3];                       /* the same for the product (INFINITY if not timed) */
+  uint32_t row_wgs_per_cu, gather_wgs_per_cu; /* chosen launch shapes */
+  double row_ms[5];                       /* best of 3 runs at 0, 2, 4, 8, 16 workgroups per CU */
+  double gather_ms[5];                    /* best of 3 runs at 2, 4, 8, 16, 32 workgroups per CU */
 } ckks_tune_report;
 
 int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out);
+
+/* Launch shapes of the HBM-bound kernels, in workgroups per compute unit: row_wgs for
+ * the row-wise kernels (0..64; 0 = one workgroup per ciphertext row, the default) and
+ * gather_wgs for the value-cache gather (1..64; default 8).  Results are identical for
+ * every setting.  CKKS_EINVAL outside those ranges. */
+int ckks_context_set_launch_shapes(ckks_ctx *ctx, uint32_t row_wgs, uint32_t gather_wgs);
+int ckks_context_get_launch_shapes(const ckks_ctx *ctx, uint32_t *row_wgs, uint32_t *gather_wgs);
+
+/* Persistence of the tuned settings (the three register blockings and the two launch
+ * shapes) in a text file at `path`, one line per (device architecture, compute units,
+ * log N, number of primes): ckks_tune_save writes this context's current settings,
+ * replacing its line or adding one and keeping the others (written to a temporary file
+ * and renamed, so a concurrent reader sees the old file or the new one; concurrent
+ * writers may lose each other's lines).  ckks_tune_load applies the line that matches
+ * this context and sets *found to 1, or leaves the settings and sets *found to 0 when
+ * the file or the line is absent.  Errors: CKKS_EINVAL (NULL arguments, or a matching
+ * line with settings this context does not support), CKKS_EIO (file not readable or
+ * writable; the message names the system error). */
+int ckks_tune_save(const ckks_ctx *ctx, const char *path);
+int ckks_tune_load(ckks_ctx *ctx, const char *path, int *found);
 
 /* ---- batched images ----
  * Encrypts many images packed in one flat pixel array (image i = pixels

@@ -21,7 +21,7 @@ CKKS_OK = 0
 CKKS_PENDING = 1
 ERRORS = {
     -1: "CKKS_EINVAL", -2: "CKKS_ENOMEM", -3: "CKKS_ENOMEM_BUDGET", -4: "CKKS_EDEVICE", -5: "CKKS_ELEVEL",
-    -6: "CKKS_ESCALE", -7: "CKKS_ECACHE", -8: "CKKS_EUNSUPPORTED", -9: "CKKS_ESTATE", -10: "CKKS_ECANCELED",
+    -6: "CKKS_ESCALE", -7: "CKKS_ECACHE", -8: "CKKS_EUNSUPPORTED", -9: "CKKS_ESTATE", -10: "CKKS_ECANCELED", -11: "CKKS_EIO",
 }
 ERRORS_BY_NAME = {v: k for k, v in ERRORS.items()}
 CKKS_CACHE_RADIX, CKKS_CACHE_VALUE_TOPK, CKKS_CACHE_VALUE_FULL = 1, 2, 3
@@ -71,7 +71,8 @@ class ckks_server_stats_t(C.Structure):
 class ckks_tune_report_t(C.Structure):
     _fields_ = [("encrypt_width", C.c_uint32), ("decrypt_width", C.c_uint32), ("trial_cts", C.c_uint32),
                 ("mul_width", C.c_uint32), ("encrypt_ms", C.c_double * 3), ("decrypt_ms", C.c_double * 3),
-                ("mul_ms", C.c_double * 3)]
+                ("mul_ms", C.c_double * 3), ("row_wgs_per_cu", C.c_uint32), ("gather_wgs_per_cu", C.c_uint32),
+                ("row_ms", C.c_double * 5), ("gather_ms", C.c_double * 5)]
 
 
 class ckks_pipeline_config_t(C.Structure):
@@ -95,6 +96,10 @@ _SIGS = {
     "ckks_ct_bytes": (C.c_uint64, [C.c_void_p, C.c_uint32]),
     "ckks_context_set_ntt_width": (C.c_int, [C.c_void_p, C.c_uint32]),
     "ckks_context_get_ntt_width": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32)]),
+    "ckks_context_set_launch_shapes": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32]),
+    "ckks_context_get_launch_shapes": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]),
+    "ckks_tune_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "ckks_tune_load": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int)]),
     "ckks_context_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                     C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "ckks_keygen": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
@@ -478,16 +483,40 @@ class Context:
 
     def autotune(self, trial_cts: int = 4096) -> dict:
         """Time the NTT register blockings for encryption, decryption and (with
-        key-switching keys) the product; keep the fastest of each."""
+        key-switching keys) the product, and the launch shapes of the row-wise kernels and
+        the value-cache gather; keep the fastest of each (ckks_autotune)."""
         r = ckks_tune_report_t()
         _check(lib().ckks_autotune(self.handle, int(trial_cts), C.byref(r)))
         out = {"encrypt_width": r.encrypt_width, "decrypt_width": r.decrypt_width, "trial_cts": r.trial_cts,
                "encrypt_ms": {8: r.encrypt_ms[0], 16: r.encrypt_ms[1], 32: r.encrypt_ms[2]},
-               "decrypt_ms": {8: r.decrypt_ms[0], 16: r.decrypt_ms[1], 32: r.decrypt_ms[2]}}
+               "decrypt_ms": {8: r.decrypt_ms[0], 16: r.decrypt_ms[1], 32: r.decrypt_ms[2]},
+               "row_wgs_per_cu": r.row_wgs_per_cu, "gather_wgs_per_cu": r.gather_wgs_per_cu,
+               "row_ms": dict(zip((0, 2, 4, 8, 16), list(r.row_ms))),
+               "gather_ms": dict(zip((2, 4, 8, 16, 32), list(r.gather_ms)))}
         if r.mul_width:
             out["mul_width"] = r.mul_width
             out["mul_ms"] = {8: r.mul_ms[0], 16: r.mul_ms[1], 32: r.mul_ms[2]}
         return out
+
+    def set_launch_shapes(self, row_wgs: int, gather_wgs: int):
+        _check(lib().ckks_context_set_launch_shapes(self.handle, int(row_wgs), int(gather_wgs)))
+
+    def launch_shapes(self) -> tuple:
+        """(row_wgs, gather_wgs): workgroups per compute unit of the row-wise kernels (0: one
+        per row) and of the value-cache gather."""
+        r, g = C.c_uint32(0), C.c_uint32(0)
+        _check(lib().ckks_context_get_launch_shapes(self.handle, C.byref(r), C.byref(g)))
+        return r.value, g.value
+
+    def tune_save(self, path: str):
+        """Store this context's tuned settings in the tuning file at path (ckks_tune_save)."""
+        _check(lib().ckks_tune_save(self.handle, os.fsencode(path)))
+
+    def tune_load(self, path: str) -> bool:
+        """Apply the tuning file's settings for this device and ring shape; False if none."""
+        found = C.c_int(0)
+        _check(lib().ckks_tune_load(self.handle, os.fsencode(path), C.byref(found)))
+        return bool(found.value)
 
 
 class Cache:

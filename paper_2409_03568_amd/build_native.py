@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libckks_mi355x.so")
 SOURCES = ["api.cpp", "host_math.cpp", "k_ntt_dispatch.cpp", "k_ops.hip", "k_cache.hip", "server.cpp", "batch.cpp",
-           "pipeline.cpp"] + ["k_ntt_%d_%s.hip" % (n, part) for n in (13, 12, 14, 11) for part in ("fused", "enc", "mul")]
+           "pipeline.cpp", "tune_file.cpp"] + ["k_ntt_%d_%s.hip" % (n, part) for n in (13, 12, 14, 11) for part in ("fused", "enc", "mul")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -435,6 +435,25 @@ int ckks_context_get_ntt_width(const ckks_ctx *ctx, uint32_t *values_per_thread)
   return CKKS_OK;
 }
 
+int ckks_context_set_launch_shapes(ckks_ctx *ctx, uint32_t row_wgs, uint32_t gather_wgs) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (row_wgs > 64) return fail(CKKS_EINVAL, "row_wgs must be 0..64");
+  if (gather_wgs < 1 || gather_wgs > 64) return fail(CKKS_EINVAL, "gather_wgs must be 1..64");
+  ctx->row_wgs = (int)row_wgs;
+  ctx->gather_wgs = (int)gather_wgs;
+  return CKKS_OK;
+}
+
+int ckks_context_get_launch_shapes(const ckks_ctx *ctx, uint32_t *row_wgs, uint32_t *gather_wgs) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!row_wgs || !gather_wgs) return fail(CKKS_EINVAL, "row_wgs/gather_wgs is NULL");
+  *row_wgs = (uint32_t)ctx->row_wgs;
+  *gather_wgs = (uint32_t)ctx->gather_wgs;
+  return CKKS_OK;
+}
+
 uint64_t ckks_ct_bytes(const ckks_ctx *ctx, uint32_t level) {
   if (!ctx || level < 1 || level > (uint32_t)ctx->prm.L) return 0;
   return ct_words(ctx, level) * sizeof(uint64_t);

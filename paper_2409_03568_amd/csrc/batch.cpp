@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "tune_file.hpp"
 
 using namespace ckks;
 
@@ -300,13 +301,18 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
   DeviceScope g(ctx->device);
   const uint32_t L = (uint32_t)ctx->prm.L;
   uint8_t *px = nullptr;
-  uint64_t *cts = nullptr;
+  uint64_t *cts = nullptr, *gout = nullptr;
   double *dec = nullptr;
   uint64_t *prod = nullptr, *scratch = nullptr;
+  uint32_t *meta = nullptr, *hits = nullptr, *counters = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void **>(&px), trial_cts);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&cts), (uint64_t)trial_cts * ckks_ct_bytes(ctx, L));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&gout), (uint64_t)trial_cts * ckks_ct_bytes(ctx, L));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&dec), (uint64_t)trial_cts * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&meta), (uint64_t)trial_cts * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&hits), (uint64_t)trial_cts * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&counters), kCountersHead * sizeof(uint32_t));
   if (e == hipSuccess && ctx->has_relin)
     e = hipMalloc(reinterpret_cast<void **>(&prod), (uint64_t)trial_cts * ckks_ct_bytes(ctx, L));
   if (e == hipSuccess && ctx->has_relin)
@@ -314,7 +320,24 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
   if (e == hipSuccess) e = hipMemset(px, 0x5a, trial_cts);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
+  // Best of three timed runs after one warm-up; `before` runs untimed ahead of each.
+  auto best_ms = [&](auto &&launch, auto &&before) {
+    double best = INFINITY;
+    for (int rep = 0; rep < 4 && e == hipSuccess; rep++) {
+      float ms = 0.f;
+      e = before();
+      if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+      if (e == hipSuccess) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && rep) best = fmin(best, ms);
+    }
+    return best;
+  };
+  auto nothing = [] { return hipSuccess; };
   const int keep_enc = ctx->logr_enc, keep_dec = ctx->logr_dec, keep_mul = ctx->logr_mul;
+  const int keep_row = ctx->row_wgs, keep_gather = ctx->gather_wgs;
   double enc_ms[3] = {INFINITY, INFINITY, INFINITY}, dec_ms[3] = {INFINITY, INFINITY, INFINITY};
   double mul_ms[3] = {INFINITY, INFINITY, INFINITY};
   for (int w = 0; w < 3 && e == hipSuccess; w++) {
@@ -326,41 +349,12 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
     job.seed0 = 0x7u;
     job.seed1 = 0x70u;
     job.out = cts;
-    for (int rep = 0; rep < 4 && e == hipSuccess; rep++) {  // first run warms up
-      float ms = 0.f;
-      e = hipEventRecord(e0, nullptr);
-      if (e == hipSuccess) e = launch_encrypt(ctx, job, trial_cts, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess && rep) enc_ms[w] = fmin(enc_ms[w], ms);
-      if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-      if (e == hipSuccess) e = launch_decrypt(ctx, cts, trial_cts, (int)L, ctx->scale, dec, 1, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess && rep) dec_ms[w] = fmin(dec_ms[w], ms);
-      if (!prod) continue;
-      if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-      if (e == hipSuccess) e = launch_mul(ctx, cts, cts, prod, trial_cts, (int)L, scratch, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess && rep) mul_ms[w] = fmin(mul_ms[w], ms);
-    }
-  }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  if (px) (void)hipFree(px);
-  if (cts) (void)hipFree(cts);
-  if (dec) (void)hipFree(dec);
-  if (prod) (void)hipFree(prod);
-  if (scratch) (void)hipFree(scratch);
-  if (e != hipSuccess) {
-    ctx->logr_enc = keep_enc;
-    ctx->logr_dec = keep_dec;
-    ctx->logr_mul = keep_mul;
-    return api_fail(CKKS_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    enc_ms[w] = best_ms([&] { return launch_encrypt(ctx, job, trial_cts, nullptr); }, nothing);
+    dec_ms[w] = best_ms([&] { return launch_decrypt(ctx, cts, trial_cts, (int)L, ctx->scale, dec, 1, nullptr); },
+                        nothing);
+    if (prod)
+      mul_ms[w] = best_ms([&] { return launch_mul(ctx, cts, cts, prod, trial_cts, (int)L, scratch, nullptr); },
+                          nothing);
   }
   int be = 0, bd = 0, bm = 0;
   for (int w = 1; w < 3; w++) {
@@ -371,6 +365,56 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
   ctx->logr_enc = 3 + be;
   ctx->logr_dec = 3 + bd;
   ctx->logr_mul = prod ? 3 + bm : keep_mul;
+  // Launch shapes.  The row-wise kernels are timed on the addition of the trial
+  // ciphertexts; the gather on a synthetic all-hit job: 16 entries and 2 pool members
+  // taken from the trial ciphertexts (canonical residues), every ciphertext a hit.
+  static const int kRow[5] = {0, 2, 4, 8, 16}, kGather[5] = {2, 4, 8, 16, 32};
+  double row_ms[5], gather_ms[5];
+  for (int i = 0; i < 5; i++) {
+    ctx->row_wgs = kRow[i];
+    row_ms[i] = best_ms([&] { return launch_add_sub(ctx, cts, cts, gout, trial_cts, (int)L, false, nullptr); }, nothing);
+  }
+  const uint32_t n_ent = std::min<uint32_t>(16, trial_cts), n_pool = std::min<uint32_t>(2, trial_cts);
+  std::vector<uint32_t> h_meta(trial_cts), h_hits(trial_cts), h_counters(kCountersHead, 0);
+  for (uint32_t i = 0; i < trial_cts; i++) {
+    h_meta[i] = ((i % n_pool) << 16) | (1 + (i * 7) % n_ent);
+    h_hits[i] = i;
+  }
+  h_counters[1] = trial_cts;
+  if (e == hipSuccess) e = hipMemcpy(meta, h_meta.data(), trial_cts * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(hits, h_hits.data(), trial_cts * sizeof(uint32_t), hipMemcpyHostToDevice);
+  ckks_cache fake;
+  fake.ctx = ctx;
+  fake.entries = cts;
+  fake.pool_cts = cts;
+  for (int i = 0; i < 5; i++) {
+    ctx->gather_wgs = kGather[i];
+    gather_ms[i] = best_ms(
+        [&] {
+          return launch_value_gather(ctx, &fake, meta, counters, hits, trial_cts, gout, nullptr, nullptr, 0);
+        },
+        [&] { return hipMemcpy(counters, h_counters.data(), kCountersHead * sizeof(uint32_t), hipMemcpyHostToDevice); });
+  }
+  int br = 0, bg = 0;
+  for (int i = 1; i < 5; i++) {
+    if (row_ms[i] < row_ms[br]) br = i;
+    if (gather_ms[i] < gather_ms[bg]) bg = i;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void *ptr : {(void *)px, (void *)cts, (void *)gout, (void *)dec, (void *)prod, (void *)scratch, (void *)meta,
+                    (void *)hits, (void *)counters})
+    if (ptr) (void)hipFree(ptr);
+  if (e != hipSuccess) {
+    ctx->logr_enc = keep_enc;
+    ctx->logr_dec = keep_dec;
+    ctx->logr_mul = keep_mul;
+    ctx->row_wgs = keep_row;
+    ctx->gather_wgs = keep_gather;
+    return api_fail(CKKS_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  }
+  ctx->row_wgs = kRow[br];
+  ctx->gather_wgs = kGather[bg];
   out->encrypt_width = 1u << ctx->logr_enc;
   out->decrypt_width = 1u << ctx->logr_dec;
   out->trial_cts = trial_cts;
@@ -380,6 +424,59 @@ int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
     out->decrypt_ms[w] = dec_ms[w];
     out->mul_ms[w] = mul_ms[w];
   }
+  out->row_wgs_per_cu = (uint32_t)ctx->row_wgs;
+  out->gather_wgs_per_cu = (uint32_t)ctx->gather_wgs;
+  for (int i = 0; i < 5; i++) {
+    out->row_ms[i] = row_ms[i];
+    out->gather_ms[i] = gather_ms[i];
+  }
+  return CKKS_OK;
+}
+
+static int tune_key(const ckks_ctx *ctx, tune::Key *k) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) return api_fail(CKKS_EDEVICE, "device properties");
+  k->arch = prop.gcnArchName;
+  for (char &c : k->arch)
+    if (c == ' ' || c == '\t') c = '_';
+  if (k->arch.empty()) k->arch = "unknown";
+  k->cus = ctx->num_cus;
+  k->log_n = ctx->prm.log_n;
+  k->L = ctx->prm.L;
+  return CKKS_OK;
+}
+
+int ckks_tune_save(const ckks_ctx *ctx, const char *path) {
+  if (!ctx || !path) return api_fail(CKKS_EINVAL, "ctx/path is NULL");
+  tune::Key k;
+  if (int rc = tune_key(ctx, &k)) return rc;
+  tune::Values v;
+  v.enc = 1 << ctx->logr_enc;
+  v.dec = 1 << ctx->logr_dec;
+  v.mul = 1 << ctx->logr_mul;
+  v.row = ctx->row_wgs;
+  v.gather = ctx->gather_wgs;
+  if (int err = tune::store(path, k, v)) return api_fail(CKKS_EIO, "tune file %s: %s", path, strerror(err));
+  return CKKS_OK;
+}
+
+int ckks_tune_load(ckks_ctx *ctx, const char *path, int *found) {
+  if (!ctx || !path || !found) return api_fail(CKKS_EINVAL, "ctx/path/found is NULL");
+  *found = 0;
+  tune::Key k;
+  if (int rc = tune_key(ctx, &k)) return rc;
+  tune::Values v;
+  bool hit = false;
+  if (int err = tune::lookup(path, k, &v, &hit)) return api_fail(CKKS_EIO, "tune file %s: %s", path, strerror(err));
+  if (!hit) return CKKS_OK;
+  if (!tune::valid(v, ctx->prm.log_n)) return api_fail(CKKS_EINVAL, "tune file %s: unsupported settings", path);
+  auto logr = [](int w) { return w == 8 ? 3 : w == 16 ? 4 : 5; };
+  ctx->logr_enc = logr(v.enc);
+  ctx->logr_dec = logr(v.dec);
+  ctx->logr_mul = logr(v.mul);
+  ctx->row_wgs = v.row;
+  ctx->gather_wgs = v.gather;
+  *found = 1;
   return CKKS_OK;
 }
 

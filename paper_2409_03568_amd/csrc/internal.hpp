@@ -123,6 +123,11 @@ struct ckks_ctx {
   int logr_enc = 4;  // 2^logr values per thread in the encryption / key kernels (4 or 5)
   int logr_dec = 4;  // the same for decryption
   int logr_mul = 4;  // the same for the ciphertext product and its keys
+  // Launch shapes of the HBM-bound kernels, in workgroups per compute unit: the row-wise
+  // kernels (add, sub, constants, rescale, radix gather; 0 = one workgroup per row) and
+  // the value-cache gather.  Results never depend on them.
+  int row_wgs = 0;
+  int gather_wgs = 8;
   int rc = 1;    // reduction class of the primes: 0 if all q < 2^40, else 1 (q < 2^50)
   ckks::LimbConsts lc{};
   ckks::LimbConsts *d_lc = nullptr;  // device copy of lc (kernels read it with scalar loads)
@@ -157,8 +162,8 @@ struct ckks_cache {
 };
 
 // Hit buckets of value-cached encryption: one per (pool member, cache slot) pair while
-// there are at most 65,536 of them (the single-workgroup scan stays short), else one
-// per pool member.
+// there are at most 65,536 of them (a scan of at most 64 blocks), else one per pool
+// member.
 inline uint32_t value_slot_buckets(const ckks_cache *cache) {
   return (uint64_t)cache->pool * cache->n_slots <= 65536 ? cache->n_slots : 1u;
 }
@@ -170,6 +175,14 @@ inline uint32_t value_scan_blocks(const ckks_cache *cache) { return (value_bucke
 constexpr uint32_t kCountersHead = 10;
 inline uint64_t value_counter_words(const ckks_cache *cache) {
   return kCountersHead + (uint64_t)value_buckets(cache) + value_scan_blocks(cache);
+}
+
+// Grid of a row-wise kernel (grid-stride loop over `rows` rows): one workgroup per row,
+// or ctx->row_wgs workgroups per compute unit when that is set.
+inline uint32_t row_grid(const ckks_ctx *c, uint64_t rows) {
+  uint64_t g = rows < (1u << 24) ? rows : (1u << 24);
+  if (c->row_wgs > 0 && g > (uint64_t)c->row_wgs * c->num_cus) g = (uint64_t)c->row_wgs * c->num_cus;
+  return (uint32_t)(g ? g : 1);
 }
 
 namespace ckks {

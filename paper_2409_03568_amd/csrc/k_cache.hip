@@ -340,7 +340,7 @@ hipError_t launch_value_gather(const ckks_ctx *c, const ckks_cache *cache, const
   // n is an upper bound of the hit count, which the kernel reads; a persistent grid claims
   // the hits per XCD (the cursors were zeroed with the counters by the metadata pass), at
   // most max_grid workgroups when another kernel is to run beside it
-  uint64_t grid = std::min<uint64_t>(n, 8 * (uint64_t)c->num_cus);
+  uint64_t grid = std::min<uint64_t>(n, (uint64_t)c->gather_wgs * c->num_cus);
   if (max_grid && grid > max_grid) grid = max_grid;
   if (grid == 0) grid = 1;
   hipLaunchKernelGGL(k_value_gather, dim3((uint32_t)grid), dim3(kThreads), 0, st, cache->entries, cache->pool_cts,
@@ -362,7 +362,7 @@ hipError_t launch_radix_gather(const ckks_ctx *c, const ckks_cache *cache, const
                                uint64_t *out, hipStream_t st) {
   const int L = c->prm.L;
   const uint64_t rows = n * 2 * (uint64_t)L;
-  hipLaunchKernelGGL(k_radix_gather, dim3(grid_for(rows, 1)), dim3(kThreads), 0, st, cache->entries, meta, rows, L,
+  hipLaunchKernelGGL(k_radix_gather, dim3(row_grid(c, rows)), dim3(kThreads), 0, st, cache->entries, meta, rows, L,
                      c->prm.log_n, cache->digits, c->d_lc, out);
   return hipGetLastError();
 }

@@ -237,18 +237,16 @@ __global__ void __launch_bounds__(kFilterThreads)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static uint32_t row_grid(uint64_t rows) { return (uint32_t)(rows < (1u << 24) ? rows : (1u << 24)); }
-
 hipError_t launch_add_sub(const ckks_ctx *c, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
                           int level, bool sub, hipStream_t st) {
   RowConsts rc{};
   for (int i = 0; i < level; i++) rc.q[i] = c->prm.q[(size_t)i];
   const uint64_t rows = n * 2 * (uint64_t)level;
   if (sub)
-    hipLaunchKernelGGL(k_add_sub<true>, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, b, out, rows, level,
+    hipLaunchKernelGGL(k_add_sub<true>, dim3(row_grid(c, rows)), dim3(kRowThreads), 0, st, a, b, out, rows, level,
                        c->prm.log_n, rc);
   else
-    hipLaunchKernelGGL(k_add_sub<false>, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, b, out, rows, level,
+    hipLaunchKernelGGL(k_add_sub<false>, dim3(row_grid(c, rows)), dim3(kRowThreads), 0, st, a, b, out, rows, level,
                        c->prm.log_n, rc);
   return hipGetLastError();
 }
@@ -262,7 +260,7 @@ hipError_t launch_mul_const(const ckks_ctx *c, const uint64_t *a, uint64_t *out,
     rc.Kp[i] = host::shoup_companion(K[i], rc.q[i]);
   }
   const uint64_t rows = n * 2 * (uint64_t)level;
-  hipLaunchKernelGGL(k_mul_const, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, out, rows, level, c->prm.log_n,
+  hipLaunchKernelGGL(k_mul_const, dim3(row_grid(c, rows)), dim3(kRowThreads), 0, st, a, out, rows, level, c->prm.log_n,
                      rc);
   return hipGetLastError();
 }
@@ -270,7 +268,7 @@ hipError_t launch_mul_const(const ckks_ctx *c, const uint64_t *a, uint64_t *out,
 hipError_t launch_add_const(const ckks_ctx *c, uint64_t *a, uint64_t n, int level, double scale, const double *d_b,
                             double b, hipStream_t st) {
   const uint64_t rows = n * (uint64_t)level;
-  hipLaunchKernelGGL(k_add_const, dim3(row_grid(rows)), dim3(kRowThreads), 0, st, a, rows, level, c->prm.log_n, scale,
+  hipLaunchKernelGGL(k_add_const, dim3(row_grid(c, rows)), dim3(kRowThreads), 0, st, a, rows, level, c->prm.log_n, scale,
                      d_b, b, c->dev.cosj, c->d_lc);
   return hipGetLastError();
 }
@@ -292,7 +290,7 @@ hipError_t launch_rescale(const ckks_ctx *c, const uint64_t *a, uint64_t *out, u
   RescaleConsts rc{};
   rescale_consts(c, level, rc.q, rc.h_mod, rc.qlinv, rc.qlinv_p, &rc.qlast, &rc.h);
   const uint64_t polys = n * 2;
-  hipLaunchKernelGGL(k_rescale, dim3(row_grid(polys)), dim3(kRowThreads), 0, st, a, out, polys, level, c->prm.log_n,
+  hipLaunchKernelGGL(k_rescale, dim3(row_grid(c, polys)), dim3(kRowThreads), 0, st, a, out, polys, level, c->prm.log_n,
                      rc);
   return hipGetLastError();
 }
