@@ -95,8 +95,9 @@ struct FusedJob {
   double *dec_out = nullptr;             // [n] decrypted slot 0 (limb 0), or NULL
   double inv_scale = 0.0;
   // ring = 0: the ciphertext of pixel t goes to out + t S.  Otherwise out holds `ring`
-  // ciphertexts and the one produced at position i of the launch's item sequence goes to
-  // slot i mod ring (only with dec_out: the ciphertexts are written in full but not kept).
+  // ciphertexts: workgroup b owns slots [b K, (b+1) K), K = ring / grid, and writes its
+  // successive items to them in turn (only with dec_out: the ciphertexts are written in
+  // full but not kept).
   uint64_t ring = 0;
 };
 

@@ -143,10 +143,10 @@ __global__ void __launch_bounds__(kThreads)
 
 // out = entry[slot] + pool[u] for cached pixels (missed pixels are written by the plain
 // encryption kernel), plus the optional fused brightness encode(b_image) on c0 (see
-// EncJob).  One workgroup per hit-list position (XCD-contiguous logical order),
-// streaming all 2L rows of that ciphertext: the hit list is grouped by pool member, so
-// each XCD works through a few pool entries at a time and they stay in its L2, while
-// the output streams past with non-temporal stores.
+// EncJob).  A persistent grid whose workgroups claim hit-list positions per XCD
+// (xcd_claim) and stream all 2L rows of each: the hit list is grouped by pool member and
+// cache slot, so each XCD works through a few (entry, pool member) pairs at a time and
+// they stay in its L2, while the output streams past with non-temporal stores.
 struct Bright {
   const uint64_t *seg_end;
   const double *seg_b;

@@ -123,6 +123,51 @@ constexpr int fused_waves_hint() {
   return MISSES ? 1 : decrypt_waves_per_eu<LOGN, LOGR>();
 }
 
+// What one item of the launch is: its position i in the item sequence (total: no item
+// left), the pixel index, the meta word of a hit or the pixel value of a miss, and the
+// brightness multiplier of its image.
+struct ItemDesc {
+  uint64_t i, item;
+  uint32_t word, miss;
+  double fb;
+};
+
+// Claims the next item of this workgroup from the XCD regions of xcd_claim, without
+// barriers (one thread calls it; `region` keeps its state).
+__device__ __forceinline__ uint64_t claim_one(uint32_t *cursor, uint64_t total, uint32_t &region) {
+  const uint32_t home = blockIdx.x % kXcds;
+  for (; region < kXcds; region++) {
+    const uint32_t x = (home + region) % kXcds;
+    const uint64_t lo = total * x / kXcds, hi = total * (x + 1) / kXcds;
+    const uint64_t i = lo + atomicAdd(&cursor[x], 1u);
+    if (i < hi) return i;
+  }
+  return total;
+}
+
+// Item i of M misses and total - M hits: a miss when floor((i+1) M / total) > floor(i M / total).
+template <bool BRIGHT, bool MISSES>
+__device__ __forceinline__ ItemDesc resolve_item(const FusedJob &job, uint64_t i, uint64_t M, uint64_t total) {
+  ItemDesc d{i, 0, 0, 0, 0.0};
+  if (i >= total) return d;
+  const uint64_t mb = i * M / total, mb1 = (i + 1) * M / total;  // i, M < 2^32: no overflow
+  if (MISSES && mb1 > mb) {
+    d.miss = 1;
+    d.item = job.miss_list ? (uint64_t)job.miss_list[mb] : mb;
+    d.word = job.px[d.item];
+  } else {
+    d.item = job.hits[i - mb];
+    d.word = job.meta[d.item];
+  }
+  if (BRIGHT) d.fb = job.seg_b[segment_of(job.seg_end, job.n_seg, job.seg_base + d.item)] * job.bright_scale;
+  return d;
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x), hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return (uint64_t)hi << 32 | lo;
+}
+
 template <int LOGN, int LOGR, int RC, bool BRIGHT, bool DECRYPT, bool MISSES>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR))
     __attribute__((amdgpu_waves_per_eu(fused_waves_hint<LOGN, LOGR, MISSES>())))
@@ -145,24 +190,35 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
   const uint64_t total = M + H;
   // ring: workgroup b owns slots [b K, (b+1) K), K = ring / grid, and cycles through them
   const uint64_t K = job.ring / gridDim.x;
-  uint64_t done = 0;
-  __shared__ uint64_t s_item;
-  uint32_t region = 0;
-  for (uint64_t i = xcd_claim(job.cursor, total, region, &s_item); i < total;
-       i = xcd_claim(job.cursor, total, region, &s_item), done++) {
-    const uint64_t mb = i * M / total, mb1 = (i + 1) * M / total;  // i, M < 2^32: no overflow
+  // Thread 0 claims and resolves the next item (dependent loads: hit list, meta word, image
+  // of the pixel) while the other waves work on the current one; the descriptors alternate
+  // between two LDS slots, and the barrier that ends an item publishes the next.
+  __shared__ ItemDesc s_desc[2];
+  __shared__ uint32_t s_region;  // claim state of thread 0 (kept in LDS: no register across the item)
+  if (tid == 0) {
+    uint32_t region = 0;
+    s_desc[0] = resolve_item<BRIGHT, MISSES>(job, claim_one(job.cursor, total, region), M, total);
+    s_region = region;
+  }
+  __syncthreads();
+  for (uint64_t done = 0;; done++) {
+    const ItemDesc &cd = s_desc[done & 1];
+    if (uniform_u64(cd.i) >= total) break;
+    const uint64_t item = uniform_u64(cd.item);
+    const uint32_t word = __builtin_amdgcn_readfirstlane(cd.word);
+    const bool miss = MISSES && __builtin_amdgcn_readfirstlane(cd.miss) != 0;
+    const double fb = BRIGHT ? __builtin_bit_cast(double, uniform_u64(__builtin_bit_cast(uint64_t, cd.fb))) : 0.0;
+    if (tid == 0) {
+      uint32_t region = s_region;
+      s_desc[(done + 1) & 1] = resolve_item<BRIGHT, MISSES>(job, claim_one(job.cursor, total, region), M, total);
+      s_region = region;
+    }
     const uint64_t ring_slot = job.ring ? blockIdx.x * K + done % K : 0;
+    uint64_t *po = job.out + (job.ring ? ring_slot : item) * S_ct;
     double k0[R], k1[R];
-    uint64_t item;
-    bool miss = false;
-    if constexpr (MISSES) miss = mb1 > mb;
     if (miss) {
       if constexpr (MISSES) {  // compiled only where misses can occur
-        item = job.miss_list ? (uint64_t)job.miss_list[mb] : mb;
-        const double value = (double)job.px[item];
-        const double fb =
-            BRIGHT ? job.seg_b[segment_of(job.seg_end, job.n_seg, job.seg_base + item)] * job.bright_scale : 0.0;
-        uint64_t *out = job.out + (job.ring ? ring_slot : item) * S_ct;
+        const double value = (double)word;
         uint32_t smp[R];
         if constexpr (S::kSmpLds)
           draw_samples<LOGN, LOGR>(smpl, cdt, B, opaque(tid), job.seed0, job.seed1, job.first_index + item, kTagV,
@@ -172,17 +228,12 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
                                    kTagV, kTagE0, kTagE1);
         double u0[R], u1[R];
         for (int l = 1; l < L; l++)
-          encrypt_limb<LOGN, LOGR, RC, BRIGHT, false>(l, lds, smpl, smp, L, B, value, fb, out, lc, dt, u0, u1);
-        encrypt_limb<LOGN, LOGR, RC, BRIGHT, DECRYPT>(0, lds, smpl, smp, L, B, value, fb, out, lc, dt, k0, k1);
+          encrypt_limb<LOGN, LOGR, RC, BRIGHT, false>(l, lds, smpl, smp, L, B, value, fb, po, lc, dt, u0, u1);
+        encrypt_limb<LOGN, LOGR, RC, BRIGHT, DECRYPT>(0, lds, smpl, smp, L, B, value, fb, po, lc, dt, k0, k1);
       }
     } else {
-      item = job.hits[i - mb];
-      const uint32_t m = job.meta[item];
-      const uint64_t *pe = job.entries + (uint64_t)((m & 0xffffu) - 1) * S_ct;
-      const uint64_t *pz = job.pool + (uint64_t)(m >> 16) * S_ct;
-      uint64_t *po = job.out + (job.ring ? ring_slot : item) * S_ct;
-      const double fb =
-          BRIGHT ? job.seg_b[segment_of(job.seg_end, job.n_seg, job.seg_base + item)] * job.bright_scale : 0.0;
+      const uint64_t *pe = job.entries + (uint64_t)((word & 0xffffu) - 1) * S_ct;
+      const uint64_t *pz = job.pool + (uint64_t)(word >> 16) * S_ct;
       double u[R];
       for (int l = 1; l < L; l++) {
         gather_row<LOGN, LOGR, BRIGHT, false>(0, l, L, pe, pz, po, fb, lc, dt, u);
@@ -195,6 +246,7 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR))
       const double s = decode_regs<LOGN, LOGR, RC>(k0, k1, lds, red, lc, dt);
       if (tid == 0) job.dec_out[item] = s * job.inv_scale;
     }
+    __syncthreads();
   }
 }
 
