@@ -371,8 +371,9 @@ def batched_bench(P, W, runs):
 
 def pipeline_bench(P, W, runs):
     """512x512 Zipf image at N=4096 / 3x36-bit: plain, radix and value-cache encryption ->
-    5x5 mean filter -> decryption, in tiles of 64 rows on three overlapped streams, against
-    the same tiles on one stream and against the whole image at once."""
+    5x5 mean filter -> decryption, in tiles of 64 rows on one stream (a ring of encrypted
+    rows) and on three overlapped streams (recomputed halos), against the whole image at
+    once."""
     import torch
 
     cfg = 5
@@ -393,7 +394,14 @@ def pipeline_bench(P, W, runs):
     R = e["k"] // 2
     pad = np.pad(img.astype(np.float64), R, mode="edge")
     box = sum(pad[dy:dy + H, dx:dx + Wd] for dy in range(e["k"]) for dx in range(e["k"])) / (e["k"] ** 2)
-    res = {"pixels": n, "k": e["k"], "tile_rows": 64, "ciphertext_GB": round(n * ctx.ct_bytes() / 1e9, 1)}
+    T = 64
+    ringrows = min(T + 2 * (e["k"] // 2), H)
+    res = {"pixels": n, "k": e["k"], "tile_rows": T, "ciphertext_GB": round(n * ctx.ct_bytes() / 1e9, 1),
+           # device buffers of the ciphertexts: one stream keeps a ring of T + 2R encrypted rows and T
+           # filtered rows; the whole image keeps every encrypted and filtered ciphertext
+           "buffer_GB": {"tiles_1_stream": round((ringrows * ctx.ct_bytes() + T * ctx.ct_bytes(c.num_primes - 1))
+                                                 * Wd / 1e9, 2),
+                         "whole_image": round(n * (ctx.ct_bytes() + ctx.ct_bytes(c.num_primes - 1)) / 1e9, 2)}}
     for name, cache in caches.items():
         row = {}
         for mode, tile, streams in (("overlap_3_streams", 64, 3), ("tiles_1_stream", 64, 1), ("whole_image", H, 1)):

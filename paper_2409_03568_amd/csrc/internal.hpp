@@ -261,9 +261,11 @@ hipError_t launch_add_const(const ckks_ctx *c, uint64_t *a, uint64_t n, int leve
 hipError_t launch_rescale(const ckks_ctx *c, const uint64_t *a, uint64_t *out, uint64_t n, int level,
                           hipStream_t stream);
 // k x k mean filter of an H x W image of ciphertexts, output rows [y0, y1) (out holds
-// y1 - y0 rows); K = the per-limb multiplier rint(q_last / k^2) mod q_i.
+// y1 - y0 rows); K = the per-limb multiplier rint(q_last / k^2) mod q_i.  Image row y is
+// read from row y mod ring_rows of `in` (0: ring_rows = H, `in` holds the whole image).
 hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
-                              uint32_t y0, uint32_t y1, uint32_t k, int level, const uint64_t *K, hipStream_t stream);
+                              uint32_t y0, uint32_t y1, uint32_t k, int level, const uint64_t *K, hipStream_t stream,
+                              uint32_t ring_rows = 0);
 
 // Fills n words with v (a kernel, so it can be captured in a graph).
 hipError_t launch_fill_u32(uint32_t *p, uint32_t n, uint32_t v, hipStream_t stream);

@@ -114,9 +114,11 @@ __global__ void __launch_bounds__(kRowThreads)
 
 // Fused k x k mean filter with clamped borders: out(y,x) = rescale(K * sum of the window).
 // Thread (x-tile, poly, j) owns XT adjacent output columns of coefficient j and walks down
-// output rows y_begin..y_end-1 of the image (written as rows 0.. of out), keeping the horizontal window sums of the last k rows in a ring; the
-// vertical sum is updated by adding the row that enters and subtracting the row that
-// leaves.  Arithmetic is exact FP64 on signed representatives:
+// output rows y_begin..y_end-1 of the image (written as rows 0.. of out), keeping the
+// horizontal window sums of the last k rows in a ring; the vertical sum is updated by
+// adding the row that enters and subtracting the row that leaves.  Image row y is read
+// from row y mod fc.ring of `in` (a buffer of whole rows: the image itself, or a ring of
+// rows that a tiled pipeline refills as it moves down).  Arithmetic is exact FP64 on signed representatives:
 //   a horizontal sum of k <= 7 canonical residues is below 7q < 2^53 and is reduced to
 //   |h| <= q/2 + 2; the vertical sum of k such values stays below 3.5q + 14 < 2^52; the
 //   product with the centered multiplier K (|K| <= q/2) has |v K / q| < 1.75q < 2^51, so
@@ -129,6 +131,7 @@ struct FilterConsts {
   double K[kMaxL];      // K = rint(q_last / k^2) mod q_i, centered
   double qlinv[kMaxL];  // q_last^-1 mod q_i, centered
   double h;             // floor(q_last / 2)
+  uint32_t ring;        // rows of the input buffer: image row y is buffer row y mod ring
 };
 
 constexpr int kFilterWaves = 8;
@@ -162,7 +165,8 @@ __global__ void __launch_bounds__(kFilterThreads)
   const uint64_t base = (uint64_t)poly * LV * N + j;
   // horizontal sums of input row yy for the XT output columns
   auto hsum = [&](int64_t yy, double (&h)[XT][LV]) {
-    const uint64_t y = (uint64_t)(yy < 0 ? 0 : (yy >= (int64_t)H ? H - 1 : yy));
+    const uint32_t yi = (uint32_t)(yy < 0 ? 0 : (yy >= (int64_t)H ? H - 1 : yy));
+    const uint64_t y = yi < fc.ring ? yi : yi % fc.ring;
     double c[XC][LV];
 #pragma unroll
     for (int d = 0; d < XC; d++) {
@@ -335,8 +339,10 @@ static double centered_double(uint64_t x, uint64_t q) {
 }
 
 hipError_t launch_mean_filter(const ckks_ctx *c, const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W,
-                              uint32_t y0, uint32_t y1, uint32_t k, int level, const uint64_t *K, hipStream_t st) {
+                              uint32_t y0, uint32_t y1, uint32_t k, int level, const uint64_t *K, hipStream_t st,
+                              uint32_t ring_rows) {
   FilterConsts fc{};
+  fc.ring = ring_rows ? ring_rows : H;
   const uint64_t qlast = c->prm.q[(size_t)level - 1];
   for (int i = 0; i < level; i++) {
     const uint64_t qi = c->prm.q[(size_t)i];

@@ -1,15 +1,23 @@
-// Streamed image pipeline: encrypt -> k x k mean filter -> decrypt over row tiles, the
-// three stages on their own streams so that tile t+1 is encrypted while tile t is
-// filtered and tile t-1 decrypted.
+// Streamed image pipeline: encrypt -> k x k mean filter -> decrypt over row tiles.
 //
-// Tile t covers output rows [r0, r1).  Its input buffer holds the encrypted rows
-// [r0 - k/2, r1 + k/2) clipped to the image: the halo rows are encrypted again for each
-// tile instead of being exchanged, which gives identical ciphertexts because every
-// ciphertext depends only on its pixel and its global Philox index (Sec. 3.3 and the
-// counter-based sampling of the encryption).  The filter computes only the tile's own
-// output rows, whose windows lie inside the buffer (at the image border the buffer ends
-// where the image does, so the clamp-edge rule applies unchanged).  Two buffers per
-// stage alternate between tiles; events order each buffer's reuse after its readers.
+// One stream (the default, also the server's job runner): the encrypted rows live in a
+// ring of T + 2R rows (tile rows T, filter radius R = k/2); image row y sits in ring row
+// y mod (T + 2R).  Tile t encrypts only the rows it adds to the ring -- rows
+// [r1 - T + R, r1 + R) of the image for output rows [r0, r1), the first tile also its
+// upper halo -- so every pixel is encrypted once, and filters its output rows straight
+// from the ring; the rows it overwrites are those no later tile reads.  The ciphertexts
+// equal the whole-image ones because every ciphertext depends only on its pixel and its
+// global Philox index (Sec. 3.3 and the counter-based sampling of the encryption).
+//
+// Three streams: the stages on their own streams, so that tile t+1 can be encrypted while
+// tile t is filtered and tile t-1 decrypted.  Tile t's input buffer holds the encrypted
+// rows [r0 - R, r1 + R) clipped to the image: the halo rows are encrypted again for each
+// tile instead of being exchanged.  The filter computes only the tile's own output rows,
+// whose windows lie inside the buffer (at the image border the buffer ends where the
+// image does, so the clamp-edge rule applies unchanged).  Two buffers per stage alternate
+// between tiles; events order each buffer's reuse after its readers.  Every launch of the
+// three stages fills the device by itself, so the overlap gains nothing measurable and the
+// recomputed halos cost their share: one stream is the faster mode.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -95,34 +103,50 @@ hipError_t run_tiles(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t
                      const uint64_t *K, double out_scale, int dec_limbs, double *d_out, void *mem, hipStream_t st) {
   const uint32_t L = (uint32_t)ctx->prm.L, R = k / 2;
   const TileSizes ts = tile_sizes(ctx, cache, H, W, k, tile_rows);
+  const uint32_t ring = ts.cap_rows;  // T + 2R rows, or the whole image
+  const uint64_t row_words = (uint64_t)W * 2 * L * ctx->N;
   uint8_t *m = static_cast<uint8_t *>(mem);
   uint64_t *enc = reinterpret_cast<uint64_t *>(m), *flt = reinterpret_cast<uint64_t *>(m + ts.enc);
   void *ws = m + ts.enc + ts.flt;
+  // image rows [a, b) into their ring rows (at most two contiguous runs)
+  auto encrypt_rows = [&](uint32_t a, uint32_t b) {
+    hipError_t e = hipSuccess;
+    while (a < b && e == hipSuccess) {
+      const uint32_t slot = a % ring, cnt = b - a < ring - slot ? b - a : ring - slot;
+      const uint64_t n = (uint64_t)cnt * W, px0 = (uint64_t)a * W;
+      uint64_t *out = enc + (uint64_t)slot * row_words;
+      if (cache) {
+        e = encrypt_cached_ws(ctx, cache, d_px + px0, n, seed0, seed1, first_index + px0, out, ws, st, true);
+      } else {
+        EncJob job;
+        job.px = d_px + px0;
+        job.n = n;
+        job.first_index = first_index + px0;
+        job.seed0 = seed0;
+        job.seed1 = seed1;
+        job.out = out;
+        e = launch_encrypt(ctx, job, n < (1u << 24) ? n : (1u << 24), st);
+      }
+      a += cnt;
+    }
+    return e;
+  };
   hipError_t e = hipSuccess;
+  uint32_t ready = 0;  // image rows [0, ready) have been encrypted
   for (uint32_t r0 = 0; r0 < H && e == hipSuccess; r0 += ts.rows) {
     const uint32_t r1 = r0 + ts.rows < H ? r0 + ts.rows : H;
-    const uint32_t s0 = r0 >= R ? r0 - R : 0, s1 = r1 + R < H ? r1 + R : H;
-    const uint64_t n_in = (uint64_t)(s1 - s0) * W, px0 = (uint64_t)s0 * W;
-    if (cache) {
-      e = encrypt_cached_ws(ctx, cache, d_px + px0, n_in, seed0, seed1, first_index + px0, enc, ws, st, true);
-    } else {
-      EncJob job;
-      job.px = d_px + px0;
-      job.n = n_in;
-      job.first_index = first_index + px0;
-      job.seed0 = seed0;
-      job.seed1 = seed1;
-      job.out = enc;
-      e = launch_encrypt(ctx, job, n_in < (1u << 24) ? n_in : (1u << 24), st);
-    }
+    const uint32_t need = r1 + R < H ? r1 + R : H;
+    e = encrypt_rows(ready, need);
+    ready = need;
     if (e != hipSuccess) break;
     if (k) {
-      e = launch_mean_filter(ctx, enc, flt, s1 - s0, W, r0 - s0, r1 - s0, k, (int)L, K, st);
+      e = launch_mean_filter(ctx, enc, flt, H, W, r0, r1, k, (int)L, K, st, ring);
       if (e == hipSuccess)
         e = launch_decrypt(ctx, flt, (uint64_t)(r1 - r0) * W, (int)L - 1, out_scale, d_out + (uint64_t)r0 * W,
                            L - 1 >= 2 ? dec_limbs : 1, st);
-    } else {
-      e = launch_decrypt(ctx, enc, n_in, (int)L, out_scale, d_out + (uint64_t)r0 * W, L >= 2 ? dec_limbs : 1, st);
+    } else {  // R = 0: the tile's rows start a ring of T rows
+      e = launch_decrypt(ctx, enc + (uint64_t)(r0 % ring) * row_words, (uint64_t)(r1 - r0) * W, (int)L, out_scale,
+                         d_out + (uint64_t)r0 * W, L >= 2 ? dec_limbs : 1, st);
     }
   }
   return e;

@@ -1,5 +1,6 @@
-"""GPU tests of the streamed image pipeline (row tiles with recomputed halos, three
-overlapped stage streams): its decrypted output must equal, bit for bit, the whole-image
+"""GPU tests of the streamed image pipeline (row tiles through a ring of encrypted rows on
+one stream, or with recomputed halos on three overlapped stage streams): its decrypted
+output must equal, bit for bit, the whole-image
 sequence encrypt -> mean filter -> decrypt through the C ABI, for every cache kind,
 window, tile height (including 1 row, a ragged last tile and one tile for the whole
 image) and stream count; and sampled outputs must equal the oracle's own computation of
@@ -52,7 +53,9 @@ def _whole(ctx, cache, px, H, W_, seed, first, k):
 
 
 @pytest.mark.parametrize("kind", ["plain", "radix", "value"])
-@pytest.mark.parametrize("k,tile,streams", [(3, 8, 3), (5, 4, 3), (5, 1, 3), (3, 37, 1), (5, 10, 1), (7, 6, 3)])
+@pytest.mark.parametrize("k,tile,streams", [(3, 8, 3), (5, 4, 3), (5, 1, 3), (7, 6, 3), (3, 37, 1), (5, 10, 1),
+                                            (7, 1, 1), (5, 1, 1), (3, 2, 1), (7, 6, 1), (5, 4, 1), (3, 36, 1),
+                                            (1, 5, 1)])
 def test_pipeline_equals_whole_image(env, kind, k, tile, streams):
     import torch
 
@@ -100,8 +103,9 @@ def _oracle_window(o, kind, entries, pool, img, seed, first, y, x, k):
     return np.stack(cts)
 
 
-@pytest.mark.parametrize("kind,k,tile", [("plain", 5, 4), ("radix", 3, 8), ("value", 7, 6)])
-def test_pipeline_sampled_against_oracle(env, oracle_mod, kind, k, tile):
+@pytest.mark.parametrize("kind,k,tile,streams", [("plain", 5, 4, 3), ("radix", 3, 8, 3), ("value", 7, 6, 3),
+                                                 ("plain", 7, 2, 1), ("radix", 5, 3, 1), ("value", 3, 5, 1)])
+def test_pipeline_sampled_against_oracle(env, oracle_mod, kind, k, tile, streams):
     import torch
 
     P, W, ctx, img, px, caches = env
@@ -117,8 +121,8 @@ def test_pipeline_sampled_against_oracle(env, oracle_mod, kind, k, tile):
         entries = {int(v): o.value_entry(int(v), cseed) for v in vals}
         pool = np.stack([o.pool_entry(u, cseed) for u in range(16)])
     seed, first = (5, 4), 23
-    _say("[gpu] pipeline vs oracle %s k=%d tile=%d" % (kind, k, tile))
-    got = ctx.image_pipeline(px, H, W_, seed, k, tile, 3, cache=caches[kind], first_index=first)
+    _say("[gpu] pipeline vs oracle %s k=%d tile=%d streams=%d" % (kind, k, tile, streams))
+    got = ctx.image_pipeline(px, H, W_, seed, k, tile, streams, cache=caches[kind], first_index=first)
     torch.cuda.synchronize()
     got = got.cpu().numpy().reshape(H, W_)
     rng = np.random.default_rng(k)
