@@ -134,6 +134,11 @@ def c1_bench(P, W, runs):
             "max_abs_err": err}
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +162,8 @@ def parse():
     ap.add_argument("--serving-budget-gb", type=float, default=160.0, help="device bytes the server may hold")
     ap.add_argument("--serving-tile-gb", type=float, default=0.0,
                     help="cap on one job's row-tile buffers in the server (0 = whole images)")
+    ap.add_argument("--serving-bypass", type=int, default=8,
+                    help="younger jobs the server may start ahead of a waiting one (0 = strict arrival order)")
     return ap.parse_args()
 
 
@@ -430,11 +437,13 @@ def pipeline_bench(P, W, runs):
     return res
 
 
-def serving_bench(P, W, n_jobs, budget_gb, tile_gb):
+def serving_bench(P, W, n_jobs, budget_gb, tile_gb, bypass):
     """Serving workload: Poisson arrivals of encrypt (full value cache) -> 3x3 mean filter ->
-    decrypt jobs on N=8192 / 4x50-bit; closed-loop saturation first, then open-loop
-    arrivals at 0.5, 0.8 and 0.95 of it; latency = host clock from submission to the
-    decrypted pixels being in host memory."""
+    decrypt jobs on N=8192 / 4x50-bit; each job alone first (its unloaded latency), then
+    closed-loop saturation, then open-loop arrivals at 0.5, 0.8 and 0.95 of it; latency =
+    host clock from submission to the decrypted pixels being in host memory, slowdown =
+    latency over the job's unloaded latency (job sizes span two orders of magnitude, so the
+    raw latency percentiles mostly reflect the size mix)."""
     import torch
 
     cfg = 4
@@ -451,11 +460,11 @@ def serving_bench(P, W, n_jobs, budget_gb, tile_gb):
     max_job = max(P.job_bytes(ctx, *im.shape, e["k"], cache, tile_bytes) for im in imgs)
     max_job_whole = max(P.job_bytes(ctx, *im.shape, e["k"], cache) for im in imgs)
     srv = P.Server(ctx, budget, max_inflight=8, filter_k=e["k"], cache=cache,
-                   max_job_pixels=max(im.size for im in imgs), tile_bytes=tile_bytes)
+                   max_job_pixels=max(im.size for im in imgs), tile_bytes=tile_bytes, max_bypass=bypass)
 
     def run(arrivals):
         t0 = time.perf_counter()
-        done = []
+        done, ids = [], {}
         for i, im in enumerate(imgs):
             if arrivals is not None:
                 while True:
@@ -464,35 +473,50 @@ def serving_bench(P, W, n_jobs, budget_gb, tile_gb):
                         break
                     done += srv.poll(64, 0)
                     time.sleep(min(dt, 5e-4))
-            srv.submit(im, W.job_seed(cfg, i))
+            ids[srv.submit(im, W.job_seed(cfg, i))] = i
         srv.drain()
         wall = time.perf_counter() - t0
         done += srv.poll(len(imgs) + 64, 0)
         assert len(done) == len(imgs) and all(r["status"] == 0 for r in done)
-        lat = np.array([(r["t_done_us"] - r["t_submit_us"]) / 1e3 for r in done])
+        lat = np.zeros(len(imgs))
+        for r in done:
+            lat[ids[r["id"]]] = (r["t_done_us"] - r["t_submit_us"]) / 1e3
         return wall, lat
 
+    def pct(lat):
+        # latency percentiles, and those of the slowdown: a job's latency over its latency alone
+        sd = lat / alone
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "slowdown_p50": round(float(np.percentile(sd, 50)), 2),
+                "slowdown_p99": round(float(np.percentile(sd, 99)), 2)}
+
     run(None)  # warm-up (pool allocations, pinned staging)
+    alone = np.zeros(len(imgs))  # each job by itself on the idle server
+    for i, im in enumerate(imgs):
+        jid = srv.submit(im, W.job_seed(cfg, i))
+        srv.drain()
+        r = srv.poll(4, 0)
+        assert len(r) == 1 and r[0]["id"] == jid and r[0]["status"] == 0
+        alone[i] = (r[0]["t_done_us"] - r[0]["t_submit_us"]) / 1e3
     wall, lat = run(None)
     sat_qps = len(imgs) / wall
     sizes = np.array([im.size for im in imgs], dtype=np.float64)
     out = {"jobs_per_point": len(imgs), "pixels_per_job_mean": round(px_total / len(imgs), 1),
            "job_pixels_p99_over_p50": round(float(np.percentile(sizes, 99) / np.percentile(sizes, 50)), 2),
+           "alone_ms": {"p50": round(float(np.percentile(alone, 50)), 2), "p99": round(float(np.percentile(alone, 99)), 2),
+                        "p99_over_p50": round(float(np.percentile(alone, 99) / np.percentile(alone, 50)), 2)},
            "max_job_GB": round(max_job / 1e9, 2), "max_job_GB_untiled": round(max_job_whole / 1e9, 2),
-           "tile_GB": tile_gb, "budget_GB": round(budget / 1e9, 1), "slots": 8,
-           "closed_loop": {"qps": round(sat_qps, 2), "px_per_s": round(px_total / wall),
-                           "p50_ms": round(float(np.percentile(lat, 50)), 2),
-                           "p99_ms": round(float(np.percentile(lat, 99)), 2)},
+           "tile_GB": tile_gb, "budget_GB": round(budget / 1e9, 1), "slots": 8, "max_bypass": bypass,
+           "closed_loop": {"qps": round(sat_qps, 2), "px_per_s": round(px_total / wall), **pct(lat)},
            "open_loop": []}
     for load in (0.5, 0.8, 0.95):
         qps = load * sat_qps
         wall, lat = run(np.cumsum(gaps) / qps)
-        out["open_loop"].append({"load": load, "qps": round(qps, 2), "px_per_s": round(px_total / wall),
-                                 "p50_ms": round(float(np.percentile(lat, 50)), 2),
-                                 "p99_ms": round(float(np.percentile(lat, 99)), 2)})
+        out["open_loop"].append({"load": load, "qps": round(qps, 2), "px_per_s": round(px_total / wall), **pct(lat)})
     st = srv.stats()
     out["peak_inflight_jobs"] = st["peak_inflight_jobs"]
     out["peak_inflight_GB"] = round(st["peak_inflight_bytes"] / 1e9, 2)
+    out["backfilled_jobs"] = st["backfilled"]
     srv.close()
     cache.close()
     ctx.close()
@@ -659,16 +683,23 @@ def main():
     ctx.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    progress("step: %.3f ms" % ms_per_step)
     if args.c1_runs > 0:
         out["c1"] = c1_bench(P, W, args.c1_runs)
+        progress("config 1 done")
     if args.batched_runs > 0:
         out["batched"] = batched_bench(P, W, args.batched_runs)
+        progress("batched done")
     if args.pipeline_runs > 0:
         out["pipeline"] = pipeline_bench(P, W, args.pipeline_runs)
+        progress("pipeline done")
     if args.matching_runs > 0:
         out["matching"] = matching_bench(P, W, args.matching_runs)
+        progress("matching done")
     if args.serving_jobs > 0:
-        out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb, args.serving_tile_gb)
+        out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb, args.serving_tile_gb,
+                                       args.serving_bypass)
+        progress("serving done")
     if args.cpu_sample > 0:
         cb = cpu_baseline(cfg, img, args.cpu_sample)
         cb.update(host_info())

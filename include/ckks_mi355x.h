@@ -430,12 +430,14 @@ void ckks_batch_plan_destroy(ckks_batch_plan *plan);
  * Encrypts an H x W image (plain, or with a radix / value cache, Sec. 2.2.2 / Sec. 3.2),
  * applies the k x k clamp-edge mean filter (Sec. 4.4.1) and decrypts, in tiles of
  * tile_rows output rows, so that only a few tiles of ciphertexts exist at any time.
- * Each tile encrypts its rows plus k/2 halo rows above and below again (the same
- * ciphertexts as a whole-image encryption, since every ciphertext depends only on its
- * pixel and global index).  With streams = 3, encryption, filtering and decryption run
- * on three streams of the context with two buffers per stage, so tile t+1 is encrypted
- * while tile t is filtered and tile t-1 decrypted; the caller's stream waits for all of
- * it.  streams = 1 runs the tiles one after another on the caller's stream.  Results
+ * streams = 1 (the faster mode) runs the tiles one after another on the caller's stream
+ * and keeps the encrypted rows in a ring of tile_rows + 2 (k/2) rows: each tile encrypts
+ * only the rows it adds, so every pixel is encrypted once.  With streams = 3, encryption,
+ * filtering and decryption run on three streams of the context with two buffers per
+ * stage, so tile t+1 can be encrypted while tile t is filtered and tile t-1 decrypted;
+ * each tile then encrypts its k/2 halo rows above and below again (the same ciphertexts
+ * as a whole-image encryption, since every ciphertext depends only on its pixel and
+ * global index), and the caller's stream waits for all of it.  Results
  * equal ckks_encrypt_* -> ckks_mean_filter -> ckks_decrypt_pixels on the whole image, bit
  * for bit.  Tile buffers come from the context's scratch pool on the caller's stream.
  * Calls on one context with streams = 3 must not overlap (they share the stage streams).
@@ -459,7 +461,10 @@ int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
  * owned by the server admits queued jobs in arrival order as soon as one of
  * `max_inflight` slots (each a HIP stream of its own) is free and a contiguous range of
  * the job's device bytes is free in the server's arena (one device allocation of
- * `hbm_budget_bytes` made at creation).  Admitted jobs run concurrently on their streams.
+ * `hbm_budget_bytes` made at creation).  While the oldest queued job waits for arena
+ * space, younger jobs that fit may start ahead of it, at most `max_bypass` of them per
+ * queued job (0 = strict arrival order), so no job waits forever.  Admitted jobs run
+ * concurrently on their streams.
  * A job runs in row tiles (as ckks_image_pipeline with one stream): its device bytes
  * (ckks_job_bytes) are its pixels, its decrypted values and the buffers of one tile --
  * encrypted rows with k/2 halo rows, filtered rows, cache metadata -- with the tile height
@@ -478,6 +483,8 @@ typedef struct {
   const ckks_cache *cache;    /* cache for encryption, NULL = plain encryption; must outlive the server */
   uint64_t max_job_pixels;    /* pinned staging sized for this many pixels per slot at creation (0 = on demand) */
   uint64_t tile_bytes;        /* cap on one job's tile buffers (0 = whole image) */
+  uint32_t max_bypass;        /* younger jobs that may start ahead of a waiting one (0 = none) */
+  uint32_t reserved;          /* 0 */
 } ckks_server_config;
 
 typedef struct {
@@ -495,6 +502,7 @@ typedef struct {
   uint64_t arena_bytes, inflight_bytes, peak_inflight_bytes;
   uint32_t peak_inflight_jobs, reserved;
   uint64_t canceled;
+  uint64_t backfilled;        /* jobs started ahead of an older waiting job */
 } ckks_server_stats;
 
 /* Creates a server and starts its dispatcher.  Needs keys on ctx; ctx (and cache) must

@@ -52,7 +52,8 @@ class ckks_cache_desc_t(C.Structure):
 
 class ckks_server_config_t(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("filter_k", C.c_uint32),
-                ("cache", C.c_void_p), ("max_job_pixels", C.c_uint64), ("tile_bytes", C.c_uint64)]
+                ("cache", C.c_void_p), ("max_job_pixels", C.c_uint64), ("tile_bytes", C.c_uint64),
+                ("max_bypass", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class ckks_job_result_t(C.Structure):
@@ -65,7 +66,8 @@ class ckks_server_stats_t(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
                 ("queued", C.c_uint64), ("inflight", C.c_uint64), ("arena_bytes", C.c_uint64),
                 ("inflight_bytes", C.c_uint64), ("peak_inflight_bytes", C.c_uint64),
-                ("peak_inflight_jobs", C.c_uint32), ("reserved", C.c_uint32), ("canceled", C.c_uint64)]
+                ("peak_inflight_jobs", C.c_uint32), ("reserved", C.c_uint32), ("canceled", C.c_uint64),
+                ("backfilled", C.c_uint64)]
 
 
 class ckks_tune_report_t(C.Structure):
@@ -469,10 +471,11 @@ class Context:
         _check(rc)
         return True
 
-    def image_pipeline(self, px, H: int, W: int, seed, k: int, tile_rows: int, streams: int = 3,
+    def image_pipeline(self, px, H: int, W: int, seed, k: int, tile_rows: int, streams: int = 1,
                        cache: "Cache | None" = None, first_index: int = 0, out=None, stream=None):
-        """Encrypt -> k x k mean filter -> decrypt of an H x W image in row tiles; returns the
-        decrypted filtered pixels (H*W doubles on the device)."""
+        """Encrypt -> k x k mean filter -> decrypt of an H x W image in row tiles (streams=1: a
+        ring of encrypted rows on the caller's stream; 3: three stage streams with recomputed
+        halos); returns the decrypted filtered pixels (H*W doubles on the device)."""
         import torch
 
         out = torch.empty(H * W, dtype=torch.float64, device=px.device) if out is None else out
@@ -607,13 +610,15 @@ def job_bytes(ctx: Context, H: int, W: int, filter_k: int, cache: "Cache | None"
 
 class Server:
     """Serving runtime over a context: jobs of encrypt -> k x k mean filter -> decrypt,
-    admitted in arrival order by device bytes into an arena of `hbm_budget_bytes`, at most
+    admitted in arrival order by device bytes into an arena of `hbm_budget_bytes` (younger
+    jobs may start ahead of a waiting one, at most `max_bypass` times per job), at most
     `max_inflight` running at once, each on its own stream."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int, max_inflight: int = 4, filter_k: int = 3,
-                 cache: "Cache | None" = None, max_job_pixels: int = 0, tile_bytes: int = 0):
+                 cache: "Cache | None" = None, max_job_pixels: int = 0, tile_bytes: int = 0, max_bypass: int = 0):
         cfg = ckks_server_config_t(int(hbm_budget_bytes), int(max_inflight), int(filter_k),
-                                   cache.handle if cache is not None else None, int(max_job_pixels), int(tile_bytes))
+                                   cache.handle if cache is not None else None, int(max_job_pixels), int(tile_bytes),
+                                   int(max_bypass), 0)
         h = C.c_void_p()
         _check(lib().ckks_server_create(ctx.handle, C.byref(cfg), C.byref(h)))
         self.handle = h

@@ -84,12 +84,16 @@ class Arena {
   std::map<uint64_t, uint64_t> used_;  // offset -> size
 };
 
-// Admission in arrival order: the oldest queued job starts as soon as a slot (a stream)
-// is free and the arena holds a contiguous range for its bytes.  A younger job never
-// overtakes an older one, so no job waits forever behind a stream of smaller ones.
+// Admission by arrival order with bounded backfilling: the oldest queued job starts as
+// soon as a slot (a stream) is free and the arena holds a contiguous range for its bytes.
+// While it does not fit, younger jobs that do fit may start ahead of it, but every queued
+// job can be overtaken at most max_bypass times; after that nothing younger starts before
+// it, so no job waits forever behind a stream of smaller ones.  max_bypass = 0 is strict
+// arrival order.
 struct Queued {
   uint64_t id;
   uint64_t bytes;
+  uint32_t bypassed = 0;  // younger jobs started ahead of this one
 };
 
 struct Admitted {
@@ -99,13 +103,15 @@ struct Admitted {
 
 class Admission {
  public:
-  Admission(uint64_t capacity, uint32_t slots, uint64_t align = 256) : arena_(capacity, align), free_slots_(slots) {}
+  Admission(uint64_t capacity, uint32_t slots, uint64_t align = 256, uint32_t max_bypass = 0)
+      : arena_(capacity, align), free_slots_(slots), max_bypass_(max_bypass) {}
 
   // A job that could never fit is refused at submission.
   bool fits_ever(uint64_t bytes) const { return arena_.round(bytes ? bytes : 1) <= arena_.capacity(); }
-  void push(uint64_t id, uint64_t bytes) { queue_.push_back({id, bytes}); }
+  void push(uint64_t id, uint64_t bytes) { queue_.push_back({id, bytes, 0}); }
 
-  // Starts queued jobs while the head fits; returns how many were started (appended to out).
+  // Starts queued jobs (appended to out) and returns how many: the oldest ones while they
+  // fit, then younger ones that fit ahead of a waiting older one within its bypass budget.
   template <class Out>
   size_t admit(Out &out) {
     size_t started = 0;
@@ -116,6 +122,28 @@ class Admission {
       queue_.pop_front();
       free_slots_--;
       started++;
+    }
+    if (queue_.empty() || free_slots_ == 0 || max_bypass_ == 0) return started;
+    // the head waits for arena space: try the younger jobs, oldest first
+    uint32_t budget = UINT32_MAX;  // smallest remaining bypass budget of the older jobs
+    for (auto it = queue_.begin(); it != queue_.end() && free_slots_ > 0;) {
+      if (it != queue_.begin()) {
+        uint64_t off = 0;
+        if (budget > 0 && arena_.alloc(it->bytes, &off)) {
+          for (auto j = queue_.begin(); j != it; ++j) j->bypassed++;
+          budget--;
+          out.push_back(Admitted{it->id, off});
+          it = queue_.erase(it);
+          free_slots_--;
+          started++;
+          backfilled_++;
+          continue;
+        }
+      }
+      const uint32_t left = it->bypassed < max_bypass_ ? max_bypass_ - it->bypassed : 0;
+      budget = left < budget ? left : budget;
+      if (budget == 0) break;
+      ++it;
     }
     return started;
   }
@@ -146,11 +174,14 @@ class Admission {
 
   size_t queued() const { return queue_.size(); }
   uint32_t free_slots() const { return free_slots_; }
+  uint64_t backfilled() const { return backfilled_; }
   const Arena &arena() const { return arena_; }
 
  private:
   Arena arena_;
   uint32_t free_slots_;
+  uint32_t max_bypass_;
+  uint64_t backfilled_ = 0;
   std::deque<Queued> queue_;
 };
 

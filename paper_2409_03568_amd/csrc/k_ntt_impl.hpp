@@ -336,10 +336,12 @@ constexpr int decrypt_waves_per_eu() {
   constexpr int w = wgs * (1 << (LOGN - LOGR)) / 256;
   return w < 1 ? 1 : w;
 }
+// The two-limb decryption keeps the same occupancy as the one-limb form: holding limb 0's
+// values across limb 1's transform costs a few spilled registers per ciphertext (stored
+// once, reloaded once), far less than losing the second workgroup per CU.
 template <int LOGN, int LOGR, int LIMBS>
 constexpr int decrypt_waves_hint() {
-  constexpr int w = decrypt_waves_per_eu<LOGN, LOGR>() / LIMBS;
-  return w < 1 ? 1 : w;
+  return decrypt_waves_per_eu<LOGN, LOGR>();
 }
 
 // d = c0 + c1 * s in limb l of ciphertext (c0, c1), returned in x in the first-pass

@@ -4,7 +4,8 @@
 // A dispatcher thread owns all device work of the server.  Under the server mutex it
 //   1. retires slots whose last event has completed (copies the decrypted values to the
 //      caller's buffer, returns the job's arena range and slot),
-//   2. starts queued jobs while the oldest one fits (Admission in arena.hpp), and
+//   2. starts queued jobs while the oldest one fits, then younger ones that fit within the
+//      waiting jobs' bypass budgets (Admission in arena.hpp), and
 //   3. sleeps until a submission arrives or, while jobs run, for a short poll interval.
 // Submissions only queue a copy of the pixels, so callers never wait for the GPU.
 #include <hip/hip_runtime.h>
@@ -76,7 +77,8 @@ struct ckks_server {
   Clock::time_point t0;
   ckks_server_stats st{};
 
-  ckks_server(uint64_t budget, uint32_t nslots) : adm(budget, nslots, kAlign), slots(nslots) {}
+  ckks_server(uint64_t budget, uint32_t nslots, uint32_t max_bypass)
+      : adm(budget, nslots, kAlign, max_bypass), slots(nslots) {}
   double now_us() const { return std::chrono::duration<double, std::micro>(Clock::now() - t0).count(); }
   uint32_t busy_slots() const {
     uint32_t b = 0;
@@ -237,7 +239,8 @@ int ckks_server_create(ckks_ctx *ctx, const ckks_server_config *cfg, ckks_server
   if (cfg->cache && cfg->cache->key_epoch != ctx->key_epoch)
     return ckks::api_fail(CKKS_ESTATE, "the cache was built under keys that have since been replaced");
   if (cfg->hbm_budget_bytes < kAlign) return ckks::api_fail(CKKS_EINVAL, "hbm_budget_bytes too small");
-  ckks_server *s = new ckks_server(cfg->hbm_budget_bytes, cfg->max_inflight);
+  if (cfg->max_bypass > 1024) return ckks::api_fail(CKKS_EINVAL, "max_bypass must be 0..1024");
+  ckks_server *s = new ckks_server(cfg->hbm_budget_bytes, cfg->max_inflight, cfg->max_bypass);
   s->ctx = ctx;
   s->key_epoch = ctx->key_epoch;
   s->dec_limbs = ckks::limb0_decode_exact(ctx, 255.0, ckks::encryption_terms(cfg->cache), cfg->filter_k != 0) ? 1 : 2;
@@ -379,6 +382,7 @@ int ckks_server_stats_get(ckks_server *s, ckks_server_stats *out) {
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->st;
   out->queued = s->adm.queued();
+  out->backfilled = s->adm.backfilled();
   out->inflight = s->busy_slots();
   out->inflight_bytes = s->adm.arena().used();
   return CKKS_OK;

@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <random>
 #include <vector>
 
@@ -134,10 +135,82 @@ static void admission_simulation(uint64_t seed) {
   }
 }
 
+// Backfilling: while the head waits for space, younger jobs that fit start ahead of it,
+// each queued job overtaken at most max_bypass times; then strict order until it starts.
+static void admission_backfill() {
+  Admission adm(100 * 256, 8, 256, 2);
+  std::vector<Admitted> out;
+  adm.push(1, 60 * 256);
+  CHECK(adm.admit(out) == 1 && out[0].id == 1);  // 40 units left
+  adm.push(2, 50 * 256);                         // does not fit yet
+  adm.push(3, 10 * 256);
+  adm.push(4, 10 * 256);
+  adm.push(5, 10 * 256);
+  CHECK(adm.admit(out) == 2 && out[1].id == 3 && out[2].id == 4);  // job 2 overtaken twice
+  CHECK(adm.backfilled() == 2 && adm.queued() == 2);
+  CHECK(adm.admit(out) == 0);  // job 5 fits (10 left) but job 2 has no bypass left
+  CHECK(adm.finish(out[0].offset));  // 70 free: job 2 starts, then job 5
+  CHECK(adm.admit(out) == 2 && out[3].id == 2 && out[4].id == 5);
+  for (int i = 1; i <= 4; i++) CHECK(adm.finish(out[i].offset));
+  CHECK(adm.arena().used() == 0);
+  // a younger job that does not fit either keeps its own budget for later ones
+  Admission b(100 * 256, 8, 256, 1);
+  std::vector<Admitted> o;
+  b.push(10, 90 * 256);
+  CHECK(b.admit(o) == 1);  // 10 left
+  b.push(11, 50 * 256);    // waits
+  b.push(12, 20 * 256);    // does not fit either
+  b.push(13, 5 * 256);     // fits: overtakes 11 and 12 (each once)
+  b.push(14, 5 * 256);     // would fit, but 11 and 12 have used their single bypass
+  CHECK(b.admit(o) == 1 && o[1].id == 13);
+  CHECK(b.admit(o) == 0 && b.queued() == 3);
+  CHECK(b.finish(o[0].offset) && b.finish(o[1].offset));
+  CHECK(b.admit(o) == 3 && o[2].id == 11 && o[3].id == 12 && o[4].id == 14);
+}
+
+// Simulated serving with backfilling: the budget holds, every job starts exactly once, and
+// no job is overtaken more than max_bypass times.
+static void admission_backfill_simulation(uint64_t seed, uint32_t max_bypass) {
+  std::mt19937_64 rng(seed);
+  const uint64_t budget = 64ull << 20;
+  Admission adm(budget, 6, 256, max_bypass);
+  std::vector<Admitted> running;
+  std::vector<uint64_t> start_order;
+  uint64_t next = 1;
+  for (int step = 0; step < 5000; step++) {
+    if (rng() % 2) adm.push(next++, 1 + rng() % (budget / 2));
+    std::vector<Admitted> now;
+    adm.admit(now);
+    for (auto &a : now) {
+      start_order.push_back(a.id);
+      running.push_back(a);
+    }
+    CHECK(adm.arena().used() <= budget && running.size() <= 6);
+    if (!running.empty() && rng() % 2) {
+      const size_t k = rng() % running.size();
+      CHECK(adm.finish(running[k].offset));
+      running[k] = running.back();
+      running.pop_back();
+    }
+  }
+  // job j is overtaken by every younger job that started before it
+  for (size_t i = 0; i < start_order.size(); i++) {
+    uint32_t over = 0;
+    for (size_t k = 0; k < i; k++) over += start_order[k] > start_order[i] ? 1 : 0;
+    CHECK(over <= max_bypass);
+  }
+  std::vector<uint64_t> sorted = start_order;  // each job at most once; queued ones later
+  std::sort(sorted.begin(), sorted.end());
+  for (size_t i = 0; i < sorted.size(); i++) CHECK(sorted[i] >= 1 && sorted[i] < next && (i == 0 || sorted[i] > sorted[i - 1]));
+  CHECK(sorted.size() + adm.queued() == next - 1);
+}
+
 int main() {
   for (uint64_t s = 1; s <= 5; s++) arena_random(s);
   admission_order();
   for (uint64_t s = 1; s <= 5; s++) admission_simulation(s);
+  admission_backfill();
+  for (uint64_t s = 1; s <= 5; s++) admission_backfill_simulation(s, (uint32_t)(s * 3));
   printf("OK\n");
   return 0;
 }

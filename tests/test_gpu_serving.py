@@ -125,6 +125,39 @@ def test_admission_budget(env):
         assert r["t_submit_us"] <= r["t_admit_us"] <= r["t_done_us"] and r["gpu_ms"] > 0
 
 
+def test_backfilling_keeps_results(env):
+    # a large job that waits for arena space lets small ones start ahead of it (at most
+    # max_bypass of them); every job's pixels equal the same job run alone
+    P, W, ctx, cache = env
+    _say("[gpu] serving backfilling")
+    big = W.zipf_image(120, 96, 96)
+    small = [W.zipf_image(121 + i, 16, 16) for i in range(6)]
+    b_big = P.job_bytes(ctx, 96, 96, 3, cache)
+    b_small = P.job_bytes(ctx, 16, 16, 3, cache)
+    budget = b_big + 3 * b_small  # the first big job leaves room for small ones, not for a second big
+    alone = {}
+    srv = P.Server(ctx, budget, max_inflight=1, filter_k=3, cache=cache)
+    for i, im in enumerate([big, big] + small):
+        srv.submit(im, (6, 4000 + i))
+        srv.drain()
+        alone[i] = srv.poll(4)[0]["pixels"].copy()
+    srv.close()
+    srv = P.Server(ctx, budget, max_inflight=4, filter_k=3, cache=cache, max_bypass=2)
+    ids = [srv.submit(im, (6, 4000 + i)) for i, im in enumerate([big, big] + small)]
+    srv.drain()
+    res = {r["id"]: r for r in srv.poll(64)}
+    st = srv.stats()
+    srv.close()
+    assert len(res) == 8 and all(r["status"] == 0 for r in res.values())
+    for i, jid in enumerate(ids):
+        assert np.array_equal(res[jid]["pixels"], alone[i]), i
+    assert st["peak_inflight_bytes"] <= budget
+    # the second big job waited for space and was overtaken at most twice
+    t2 = res[ids[1]]["t_admit_us"]
+    assert sum(1 for j in ids[2:] if res[j]["t_admit_us"] < t2) <= 2
+    assert st["backfilled"] <= 2  # only the waiting big job is ever overtaken (small jobs are equal)
+
+
 def test_jobs_overlap(env):
     # jobs submitted together run side by side: each takes milliseconds on the device,
     # far longer than the submissions, and the budget holds three of them
