@@ -144,7 +144,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=2048,
+    ap.add_argument("--cpu-sample", type=int, default=6144,
                     help="pixels in the oracle's timed sample of config 2 (configs 1 and 5 scale with it; 0 = skip)")
     ap.add_argument("--c1-runs", type=int, default=20, help="timed runs of config 1 (0 = skip)")
     ap.add_argument("--phases", default="plain,radix,value,filter,decrypt")
