@@ -606,8 +606,9 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     names = ["plain", "radix", "value", "filter", "decrypt"]
+    # a phase left out of --phases reports 0 (its events bracket no work)
     phase_ms = {nm: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(args.steps)]))
-                for i, nm in enumerate(names)}
+                if nm in phases else 0.0 for i, nm in enumerate(names)}
     step_ms = float(np.mean([evs[s][0].elapsed_time(evs[s][5]) for s in range(args.steps)]))
     ms_per_step = wall * 1000.0 / args.steps
     S = ctx.ct_bytes()

@@ -219,7 +219,8 @@ hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const
   }
   // The misses (compute-bound full encryptions) run on the auxiliary stream beside the hit
   // gather (bound by HBM writes); both grids are bounded so that every CU holds one
-  // encryption workgroup and two gather workgroups at once.
+  // encryption workgroup and one gather workgroup at once (of 1/2, 3/4, 1, 2 or 3 gather
+  // workgroups per CU, one balanced the two streams best).
   hipEvent_t fork = nullptr, join = nullptr;
   e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
@@ -228,7 +229,7 @@ hipError_t encrypt_cached_ws(const ckks_ctx *ctx, const ckks_cache *cache, const
   if (e == hipSuccess) e = launch_encrypt(ctx, job, std::min<uint64_t>(n, (uint64_t)ctx->num_cus), ctx->aux);
   if (e == hipSuccess) e = hipEventRecord(join, ctx->aux);
   if (e == hipSuccess)
-    e = launch_value_gather(ctx, cache, meta, counters, hits, n, out, nullptr, st, 2 * (uint64_t)ctx->num_cus);
+    e = launch_value_gather(ctx, cache, meta, counters, hits, n, out, nullptr, st, (uint64_t)ctx->num_cus);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
   // events may be destroyed while their work is pending; the runtime releases them after
   if (fork) (void)hipEventDestroy(fork);
