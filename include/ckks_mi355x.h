@@ -466,13 +466,13 @@ int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
  * queued job (0 = strict arrival order), so no job waits forever.  Admitted jobs run
  * concurrently on their streams.
  * A job runs in row tiles (as ckks_image_pipeline with one stream): its device bytes
- * (ckks_job_bytes) are its pixels, its decrypted values and the buffers of one tile --
- * encrypted rows with k/2 halo rows, filtered rows, cache metadata -- with the tile height
- * the largest whose buffers fit `tile_bytes` (0 = the whole image as one tile), so a large
- * image does not hold most of the arena while smaller jobs wait.  A job's results do not
- * depend on which other jobs run beside it, nor on the tiling: its ciphertexts are fixed by
- * (job_seed, first_index), halo rows are encrypted again bit-identically, and every
- * kernel's result is independent of the launch that computes it.
+ * (ckks_job_bytes) are its pixels, its decrypted values and the buffers of one tile -- a
+ * ring of tile + 2 (k/2) encrypted rows, the filtered rows, cache metadata -- with the
+ * tile height the largest whose buffers fit `tile_bytes` (0 = the whole image as one
+ * tile), so a large image does not hold most of the arena while smaller jobs wait.  A
+ * job's results do not depend on which other jobs run beside it, nor on the tiling: its
+ * ciphertexts are fixed by (job_seed, first_index), and every kernel's result is
+ * independent of the launch that computes it.
  */
 typedef struct ckks_server ckks_server;
 
