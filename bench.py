@@ -264,9 +264,9 @@ def matching_bench(P, W, runs):
 
 def cpu_baseline(cfg, img, sample):
     """The oracle as it stands, on the host cores, over a bounded sample of the same work:
-    `sample` random pixels of the configuration's image through its steps (plain
-    encryption and decryption for config 1; plain, radix and value encryption, the k x k
-    filter and decryption for configs 2 and 5), caches prebuilt as on the GPU."""
+    `sample` random pixels of the workload's image through its steps (plain encryption and
+    decryption for the 32x32 image; plain, radix and value encryption, the k x k filter and
+    decryption for the 256x256 and 512x512 images), caches prebuilt as on the GPU."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
@@ -320,8 +320,9 @@ def cpu_baseline(cfg, img, sample):
         "unit": "pixel-ciphertexts/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "%d random pixels of the config-%d image through %s (%d host threads, caches prebuilt; %.1f s)"
-                  % (len(idx), cfg, steps, threads, total),
+        "sample": "%d random pixels of the %dx%d %s image (N=%d, %d primes) through %s (%d host threads, caches "
+                  "prebuilt; %.1f s)" % (len(idx), img.shape[0], img.shape[1], e.get("image", "uniform"), 1 << c.log_n,
+                                         c.num_primes, steps, threads, total),
         "phase_s": {k2: round(v, 3) for k2, v in t.items()},
     }
 
