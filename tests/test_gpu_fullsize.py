@@ -1,0 +1,183 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations bench.py times,
+on outputs the oracle computes one by one:
+
+* the batched workload -- 64 RGB images (sides log-uniform in 32..512, 5.5 M pixel
+  ciphertexts at N = 8192, 4 x 50-bit primes), full value cache with a pool of 256, each
+  image's brightness, one persistent launch through a 65,536-ciphertext ring, replayed as
+  a HIP graph: sampled decrypted pixels equal the oracle's decryption of its own
+  value-cached encryption + add_const (within 1e-9), and every pixel decrypts within
+  1e-6 of pixel + brightness;
+* the streamed 512 x 512 image (N = 4096, 3 x 36-bit primes) with a top-64 value cache
+  and a 5 x 5 filter in 64-row tiles on one stream: sampled outputs equal the oracle's
+  window encryption, filter and decryption (within 1e-9);
+* one 384 x 384 serving job (the largest side of the serving mix) at N = 8192 with a full
+  value cache and a 3 x 3 filter: sampled outputs equal the oracle's (within 1e-9)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_03568_amd as P
+    from paper_2409_03568_amd import workloads as W
+
+    return P, W
+
+
+def _value_ct(o, entries, pool, npool, cseed, img_px, job, t):
+    """The oracle's value-cached ciphertext of pixel index t (entries and pool members
+    computed on demand; a value outside `entries` is encrypted in full)."""
+    p = int(img_px)
+    u = o.pool_pick(job, t, npool)
+    if not pool["have"][u]:
+        pool["cts"][u] = o.pool_entry(u, cseed)
+        pool["have"][u] = True
+    if p in entries and entries[p] is None:
+        entries[p] = o.value_entry(p, cseed)
+    return o.value_encrypt(entries.get(p), pool["cts"], npool, p, job, t)
+
+
+def test_batched_full_size_sampled(mods, oracle_mod):
+    import torch
+
+    P, W = mods
+    c = W.CONFIGS[3]
+    e = c.extras
+    imgs, b = W.batched_rgb_images(e["seed"], e["count"], e["lo"], e["hi"])
+    px = np.concatenate([im.reshape(-1) for im in imgs])
+    ends = np.cumsum([im.size for im in imgs]).astype(np.uint64)
+    per_ct = np.repeat(b.astype(np.float64), [im.size for im in imgs])
+    n = px.size
+    _say("[gpu] full-size batch: %d images, %d ciphertexts" % (len(imgs), n))
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    ctx.keygen(W.keygen_seed(3))
+    cseed, job = W.cache_seed(3), W.job_seed(3)
+    cache = ctx.cache_build(P.CKKS_CACHE_VALUE_FULL, zero_pool=e["pool"], seed=cseed)
+    plan = P.BatchPlan(ctx, cache, 65536, use_graph=True)
+    d_px = torch.from_numpy(px).cuda()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    plan.run(d_px, ends, b.astype(np.float64), job, 0, out=out)  # eager run + capture
+    torch.cuda.synchronize()
+    first = out.cpu().numpy().copy()
+    out.fill_(-1.0)
+    plan.run(d_px, ends, b.astype(np.float64), job, 0, out=out)  # graph replay
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.array_equal(got, first)
+    assert np.max(np.abs(got - (px.astype(np.float64) + per_ct))) < 1e-6
+    o = oracle_mod.Oracle(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    o.keygen(W.keygen_seed(3))
+    npool = e["pool"]
+    pool = {"cts": np.zeros((npool, o.ct_words()), dtype=np.uint64), "have": [False] * npool}
+    entries = {v: None for v in range(256)}  # the full cache holds every value
+    rng = np.random.default_rng(303)
+    idx = sorted(set([0, n - 1] + [int(ends[i]) - 1 for i in range(0, len(ends), 9)] +
+                     [int(t) for t in rng.integers(0, n, 16)]))
+    for t in idx:
+        ct = _value_ct(o, entries, pool, npool, cseed, px[t], job, t)
+        ref = o.decrypt(o.add_const(ct, float(per_ct[t])))
+        assert abs(got[t] - ref) < 1e-9, (t, got[t], ref)
+    plan.close()
+    cache.close()
+    ctx.close()
+    del d_px, out
+    torch.cuda.empty_cache()
+
+
+def _window(o, entries, pool, npool, cseed, img, job, first, y, x, k):
+    H, W_ = img.shape
+    R = k // 2
+    cts = []
+    for dy in range(-R, R + 1):
+        for dx in range(-R, R + 1):
+            yy, xx = min(max(y + dy, 0), H - 1), min(max(x + dx, 0), W_ - 1)
+            t = first + yy * W_ + xx
+            cts.append(_value_ct(o, entries, pool, npool, cseed, img[yy, xx], job, t))
+    return np.stack(cts)
+
+
+def test_pipeline_full_size_sampled(mods, oracle_mod):
+    import torch
+
+    P, W = mods
+    c = W.CONFIGS[5]
+    e = c.extras
+    img = W.config_image(5)
+    H, W_ = img.shape
+    k = e["k"]
+    _say("[gpu] full-size pipeline: %dx%d, k=%d, 64-row tiles, one stream" % (H, W_, k))
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    ctx.keygen(W.keygen_seed(5))
+    cseed, job = W.cache_seed(5), W.job_seed(5)
+    px = torch.from_numpy(img.reshape(-1)).cuda()
+    cache = ctx.cache_build(P.CKKS_CACHE_VALUE_TOPK, topk=e["topk"], zero_pool=e["pool"], scan_px=px, seed=cseed)
+    got = ctx.image_pipeline(px, H, W_, job, k, 64, 1, cache=cache)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().reshape(H, W_)
+    o = oracle_mod.Oracle(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    o.keygen(W.keygen_seed(5))
+    npool = e["pool"]
+    pool = {"cts": np.zeros((npool, o.ct_words()), dtype=np.uint64), "have": [False] * npool}
+    entries = {v: None for v in o.topk(o.histogram(img.reshape(-1)), e["topk"])}
+    rng = np.random.default_rng(505)
+    pts = {(0, 0), (H - 1, W_ - 1), (63, 100), (64, 100), (H - 1, 0)} | {
+        (int(a), int(b)) for a, b in zip(rng.integers(0, H, 4), rng.integers(0, W_, 4))}
+    for (y, x) in sorted(pts):
+        win = _window(o, entries, pool, npool, cseed, img, job, 0, y, x, k)
+        ref, sc = o.mean_filter_pixel(win, k, k, k, k // 2, k // 2)
+        val = o.decrypt(ref, level=c.num_primes - 1, scale=sc)
+        assert abs(got[y, x] - val) < 1e-9, (y, x, got[y, x], val)
+    cache.close()
+    ctx.close()
+    del px
+    torch.cuda.empty_cache()
+
+
+def test_serving_largest_job_sampled(mods, oracle_mod):
+    P, W = mods
+    c = W.CONFIGS[4]
+    e = c.extras
+    img = W.zipf_image(404, 384, 384)
+    H, W_ = img.shape
+    k = e["k"]
+    _say("[gpu] full-size serving job: %dx%d, k=%d" % (H, W_, k))
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    ctx.keygen(W.keygen_seed(4))
+    cseed, job = W.cache_seed(4), W.job_seed(4, 7)
+    cache = ctx.cache_build(P.CKKS_CACHE_VALUE_FULL, zero_pool=e["pool"], seed=cseed)
+    budget = P.job_bytes(ctx, H, W_, k, cache) + (1 << 30)
+    srv = P.Server(ctx, budget, max_inflight=2, filter_k=k, cache=cache)
+    srv.submit(img, job)
+    srv.drain()
+    res = srv.poll(4)
+    srv.close()
+    assert len(res) == 1 and res[0]["status"] == 0
+    got = res[0]["pixels"]
+    o = oracle_mod.Oracle(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    o.keygen(W.keygen_seed(4))
+    npool = e["pool"]
+    pool = {"cts": np.zeros((npool, o.ct_words()), dtype=np.uint64), "have": [False] * npool}
+    entries = {v: None for v in range(256)}
+    rng = np.random.default_rng(404)
+    pts = {(0, 0), (H - 1, W_ - 1), (H // 2, W_ // 2)} | {
+        (int(a), int(b)) for a, b in zip(rng.integers(0, H, 3), rng.integers(0, W_, 3))}
+    for (y, x) in sorted(pts):
+        win = _window(o, entries, pool, npool, cseed, img, job, 0, y, x, k)
+        ref, sc = o.mean_filter_pixel(win, k, k, k, k // 2, k // 2)
+        val = o.decrypt(ref, level=c.num_primes - 1, scale=sc)
+        assert abs(got[y, x] - val) < 1e-9, (y, x, got[y, x], val)
+    cache.close()
+    ctx.close()
