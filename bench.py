@@ -162,6 +162,7 @@ def parse():
     ap.add_argument("--serving-budget-gb", type=float, default=160.0, help="device bytes the server may hold")
     ap.add_argument("--serving-tile-gb", type=float, default=0.0,
                     help="cap on one job's row-tile buffers in the server (0 = whole images)")
+    ap.add_argument("--serving-slots", type=int, default=8, help="jobs the server runs at once (streams)")
     ap.add_argument("--serving-bypass", type=int, default=8,
                     help="younger jobs the server may start ahead of a waiting one (0 = strict arrival order)")
     return ap.parse_args()
@@ -438,7 +439,7 @@ def pipeline_bench(P, W, runs):
     return res
 
 
-def serving_bench(P, W, n_jobs, budget_gb, tile_gb, bypass):
+def serving_bench(P, W, n_jobs, budget_gb, tile_gb, bypass, slots=8):
     """Serving workload: Poisson arrivals of encrypt (full value cache) -> 3x3 mean filter ->
     decrypt jobs on N=8192 / 4x50-bit; each job alone first (its unloaded latency), then
     closed-loop saturation, then open-loop arrivals at 0.5, 0.8 and 0.95 of it; latency =
@@ -460,7 +461,7 @@ def serving_bench(P, W, n_jobs, budget_gb, tile_gb, bypass):
     tile_bytes = int(tile_gb * 1e9)
     max_job = max(P.job_bytes(ctx, *im.shape, e["k"], cache, tile_bytes) for im in imgs)
     max_job_whole = max(P.job_bytes(ctx, *im.shape, e["k"], cache) for im in imgs)
-    srv = P.Server(ctx, budget, max_inflight=8, filter_k=e["k"], cache=cache,
+    srv = P.Server(ctx, budget, max_inflight=slots, filter_k=e["k"], cache=cache,
                    max_job_pixels=max(im.size for im in imgs), tile_bytes=tile_bytes, max_bypass=bypass)
 
     def run(arrivals):
@@ -507,7 +508,7 @@ def serving_bench(P, W, n_jobs, budget_gb, tile_gb, bypass):
            "alone_ms": {"p50": round(float(np.percentile(alone, 50)), 2), "p99": round(float(np.percentile(alone, 99)), 2),
                         "p99_over_p50": round(float(np.percentile(alone, 99) / np.percentile(alone, 50)), 2)},
            "max_job_GB": round(max_job / 1e9, 2), "max_job_GB_untiled": round(max_job_whole / 1e9, 2),
-           "tile_GB": tile_gb, "budget_GB": round(budget / 1e9, 1), "slots": 8, "max_bypass": bypass,
+           "tile_GB": tile_gb, "budget_GB": round(budget / 1e9, 1), "slots": slots, "max_bypass": bypass,
            "closed_loop": {"qps": round(sat_qps, 2), "px_per_s": round(px_total / wall), **pct(lat)},
            "open_loop": []}
     for load in (0.5, 0.8, 0.95):
@@ -700,7 +701,7 @@ def main():
         progress("matching done")
     if args.serving_jobs > 0:
         out["serving"] = serving_bench(P, W, args.serving_jobs, args.serving_budget_gb, args.serving_tile_gb,
-                                       args.serving_bypass)
+                                       args.serving_bypass, args.serving_slots)
         progress("serving done")
     if args.cpu_sample > 0:
         cb = cpu_baseline(cfg, img, args.cpu_sample)
