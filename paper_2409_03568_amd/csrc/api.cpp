@@ -473,6 +473,7 @@ int ckks_context_info(const ckks_ctx *ctx, uint32_t *log_n, uint32_t *num_primes
 }
 
 int ckks_keygen(ckks_ctx *ctx, const uint64_t seed[2]) {
+  TraceRange trace_range_("ckks_keygen");
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (!seed) return fail(CKKS_EINVAL, "seed is NULL");
@@ -500,6 +501,7 @@ int ckks_keys_export(ckks_ctx *ctx, int64_t *host_s, uint64_t *host_pk) {
 }
 
 int ckks_relin_keygen(ckks_ctx *ctx, const uint64_t seed[2]) {
+  TraceRange trace_range_("ckks_relin_keygen");
   int rc = check_keys(ctx);
   if (rc) return rc;
   if (!seed) return fail(CKKS_EINVAL, "seed is NULL");
@@ -555,6 +557,7 @@ int ckks_keys_import(ckks_ctx *ctx, const int64_t *host_s, const uint64_t *host_
 
 int ckks_encrypt_pixels(ckks_ctx *ctx, const uint8_t *d_px, uint64_t n, const uint64_t seed[2],
                         uint64_t first_index, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_encrypt_pixels");
   int rc = check_keys(ctx);
   if (rc) return rc;
   if (!seed || !out) return fail(CKKS_EINVAL, "seed/out is NULL");
@@ -580,6 +583,7 @@ int ckks_encrypt_pixels(ckks_ctx *ctx, const uint8_t *d_px, uint64_t n, const ui
 
 int ckks_cache_build(ckks_ctx *ctx, const ckks_cache_desc *desc, const uint8_t *d_scan, uint64_t n_scan,
                      const uint64_t cache_seed[2], ckks_cache **out, void *stream) {
+  TraceRange trace_range_("ckks_cache_build");
   int rc = check_keys(ctx);
   if (rc) return rc;
   if (!desc || !cache_seed || !out) return fail(CKKS_EINVAL, "desc/seed/out is NULL");
@@ -835,6 +839,7 @@ int ckks_cache_import(ckks_ctx *ctx, const ckks_cache_desc *desc, uint32_t n_ent
 
 int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
                         const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_encrypt_cached");
   int rc = check_keys(ctx);
   if (rc) return rc;
   if ((rc = check_cache(ctx, cache))) return rc;
@@ -858,6 +863,7 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
 
 int ckks_encrypt_cached_noalloc(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
                                 const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_encrypt_cached_noalloc");
   int rc = check_keys(ctx);
   if (rc) return rc;
   if ((rc = check_cache(ctx, cache))) return rc;
@@ -910,6 +916,7 @@ static int binary_common(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_ba
 }
 
 int ckks_add(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_add");
   int rc = binary_common(ctx, a, b, out);
   if (rc) return rc;
   const ckks_ct_batch av = *a;
@@ -923,6 +930,7 @@ int ckks_add(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
 }
 
 int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_sub");
   int rc = binary_common(ctx, a, b, out);
   if (rc) return rc;
   const ckks_ct_batch av = *a;
@@ -936,6 +944,7 @@ int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
 }
 
 int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_mul");
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if ((rc = check_batch(ctx, a, "a")) || (rc = check_batch(ctx, b, "b"))) return rc;
@@ -968,6 +977,7 @@ int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
 }
 
 int ckks_mul_const(ckks_ctx *ctx, const ckks_ct_batch *a, double c, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_mul_const");
   int rc = check_ctx(ctx);
   if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
   if ((rc = check_out(ctx, out, a->count, a->level))) return rc;
@@ -985,6 +995,7 @@ int ckks_mul_const(ckks_ctx *ctx, const ckks_ct_batch *a, double c, ckks_ct_batc
 }
 
 int ckks_add_const(ckks_ctx *ctx, ckks_ct_batch *a, const double *d_b, double b, void *stream) {
+  TraceRange trace_range_("ckks_add_const");
   int rc = check_ctx(ctx);
   if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
   if (!d_b && !isfinite(b)) return fail(CKKS_EINVAL, "b is not finite");
@@ -995,6 +1006,7 @@ int ckks_add_const(ckks_ctx *ctx, ckks_ct_batch *a, const double *d_b, double b,
 }
 
 int ckks_rescale(ckks_ctx *ctx, const ckks_ct_batch *a, ckks_ct_batch *out, void *stream) {
+  TraceRange trace_range_("ckks_rescale");
   int rc = check_ctx(ctx);
   if (rc || (rc = check_batch(ctx, a, "a"))) return rc;
   if (a->level < 2) return fail(CKKS_ELEVEL, "rescale needs level >= 2");
@@ -1013,6 +1025,7 @@ int ckks_rescale(ckks_ctx *ctx, const ckks_ct_batch *a, ckks_ct_batch *out, void
 
 int ckks_mean_filter(ckks_ctx *ctx, const ckks_ct_batch *img, uint32_t H, uint32_t W, uint32_t k, ckks_ct_batch *out,
                      void *stream) {
+  TraceRange trace_range_("ckks_mean_filter");
   int rc = check_ctx(ctx);
   if (rc || (rc = check_batch(ctx, img, "img"))) return rc;
   if (k != 1 && k != 3 && k != 5 && k != 7) return fail(CKKS_EUNSUPPORTED, "window k must be 1, 3, 5 or 7");
@@ -1037,6 +1050,7 @@ int ckks_mean_filter(ckks_ctx *ctx, const ckks_ct_batch *img, uint32_t H, uint32
 }
 
 int ckks_decrypt_pixels(ckks_ctx *ctx, const ckks_ct_batch *in, double *d_out, void *stream) {
+  TraceRange trace_range_("ckks_decrypt_pixels");
   int rc = check_keys(ctx);
   if (rc || (rc = check_batch(ctx, in, "in"))) return rc;
   if (in->count && !d_out) return fail(CKKS_EINVAL, "d_out is NULL");

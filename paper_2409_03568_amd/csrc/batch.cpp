@@ -185,6 +185,7 @@ int ckks_batch_plan_create(ckks_ctx *ctx, const ckks_cache *cache, const ckks_ba
 int ckks_batch_run(ckks_batch_plan *p, const uint8_t *d_px, uint64_t n, const uint64_t *host_seg_end,
                    const double *host_seg_b, uint32_t n_seg, const uint64_t seed[2], uint64_t first_index,
                    double *d_out, ckks_ct_batch *cts_out, void *stream) {
+  TraceRange trace_range_("ckks_batch_run");
   if (!p || !seed) return api_fail(CKKS_EINVAL, "plan/seed is NULL");
   ckks_ctx *c = p->ctx;
   if (p->key_epoch != c->key_epoch) return api_fail(CKKS_ESTATE, "the keys were replaced after the plan was made");
@@ -295,6 +296,7 @@ void ckks_batch_plan_destroy(ckks_batch_plan *p) {
 }
 
 int ckks_autotune(ckks_ctx *ctx, uint32_t trial_cts, ckks_tune_report *out) {
+  TraceRange trace_range_("ckks_autotune");
   if (!ctx || !out) return api_fail(CKKS_EINVAL, "ctx/out is NULL");
   if (!ctx->has_keys) return api_fail(CKKS_ESTATE, "no keys on the context");
   if (trial_cts < 1 || trial_cts > (1u << 20)) return api_fail(CKKS_EINVAL, "trial_cts must be 1..2^20");

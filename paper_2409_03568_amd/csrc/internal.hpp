@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/ckks_mi355x.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include "host_math.hpp"
 
 #define CKKS_SEG_HD __host__ __device__
@@ -187,6 +188,15 @@ inline uint32_t row_grid(const ckks_ctx *c, uint64_t rows) {
 }
 
 namespace ckks {
+
+// A named range around each C-ABI call and each server job, for profilers that record
+// markers (rocprofv3 --marker-trace); without one attached a range costs two calls.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // Records a message for ckks_last_error() (thread-local) and returns `code`.
 int api_fail(int code, const char *fmt, ...);

@@ -157,6 +157,7 @@ hipError_t run_tiles(const ckks_ctx *ctx, const ckks_cache *cache, const uint8_t
 extern "C" int ckks_image_pipeline(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint32_t H,
                                    uint32_t W, const uint64_t seed[2], uint64_t first_index,
                                    const ckks_pipeline_config *cfg, double *d_out, void *stream) {
+  TraceRange trace_range_("ckks_image_pipeline");
   if (!ctx || !cfg || !seed) return api_fail(CKKS_EINVAL, "ctx/cfg/seed is NULL");
   if (!ctx->has_keys) return api_fail(CKKS_ESTATE, "no keys on the context");
   if (cache && cache->ctx != ctx) return api_fail(CKKS_ECACHE, "cache belongs to another context");

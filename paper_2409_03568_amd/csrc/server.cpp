@@ -119,6 +119,7 @@ hipError_t ensure_pinned(Slot &sl, uint64_t n) {
 // tile by tile in the job's arena range, decrypted values out; returns the status of the
 // first failing step (or the injected failure, before any device work).
 int launch_job(ckks_server *s, Slot &sl) {
+  ckks::TraceRange trace_range_("server job");
   const Job &j = sl.job;
   if (j.forced_status) return j.forced_status;
   ckks_ctx *ctx = s->ctx;
