@@ -261,6 +261,49 @@ bool limb0_decode_exact(const ckks_ctx *c, double value_bound, double terms, boo
   return x < 0.49 * (double)c->prm.q[0];
 }
 
+hipError_t WsLease::get(uint64_t bytes, void **out) {
+  size_t i = 0;
+  while (i < c_->ws.size() && c_->ws[i].stream != st_) i++;
+  if (i == c_->ws.size()) {
+    StreamWorkspace w;
+    w.stream = st_;
+    const hipError_t e = hipEventCreateWithFlags(&w.last, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    c_->ws.push_back(w);
+  }
+  StreamWorkspace &w = c_->ws[i];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      hipError_t e = hipEventSynchronize(w.last);
+      if (e == hipSuccess) e = hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    const uint64_t want = (bytes + bytes / 2 + (2ull << 20) - 1) / (2ull << 20) * (2ull << 20);
+    const hipError_t e = hipMalloc(&w.ptr, want);
+    if (e != hipSuccess) {
+      w.ptr = nullptr;
+      return e;
+    }
+    w.bytes = want;
+  }
+  const hipError_t e = hipStreamWaitEvent(st_, w.last, 0);
+  if (e != hipSuccess) return e;
+  w_ = &w;
+  *out = w.ptr;
+  return hipSuccess;
+}
+
+void ws_free_all(ckks_ctx *c) {
+  std::lock_guard<std::mutex> lk(c->ws_mu);
+  for (StreamWorkspace &w : c->ws) {
+    if (w.ptr) (void)hipFree(w.ptr);
+    if (w.last) (void)hipEventDestroy(w.last);
+  }
+  c->ws.clear();
+}
+
 int api_fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -413,6 +456,7 @@ void ckks_context_destroy(ckks_ctx *ctx) {
   for (hipStream_t &st : ctx->pipe)
     if (st) (void)hipStreamDestroy(st);
   if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  ws_free_all(ctx);
   free_tables(ctx);
   if (ctx->pool) (void)hipMemPoolDestroy(ctx->pool);
   delete ctx;
@@ -854,10 +898,10 @@ int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
   void *ws = nullptr;
-  HIP_TRY(hipMallocFromPoolAsync(&ws, cached_ws_bytes(cache, n), ctx->pool, st), "workspace alloc");
+  WsLease lease(ctx, st);
+  HIP_TRY(lease.get(cached_ws_bytes(cache, n), &ws), "workspace alloc");
   HIP_TRY(encrypt_cached_ws(ctx, cache, d_px, n, seed[0], seed[1], first_index, out->data, ws, st, true),
           "cached encryption");
-  HIP_TRY(hipFreeAsync(ws, st), "workspace free");
   return CKKS_OK;
 }
 
@@ -968,11 +1012,9 @@ int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
   void *ws = nullptr;
-  HIP_TRY(hipMallocFromPoolAsync(&ws, mul_scratch_words(av.count, (int)av.level, ctx->N) * sizeof(uint64_t), ctx->pool,
-                                 st),
-          "workspace alloc");
+  WsLease lease(ctx, st);
+  HIP_TRY(lease.get(mul_scratch_words(av.count, (int)av.level, ctx->N) * sizeof(uint64_t), &ws), "workspace alloc");
   HIP_TRY(launch_mul(ctx, av.data, bd, out->data, av.count, (int)av.level, static_cast<uint64_t *>(ws), st), "mul");
-  HIP_TRY(hipFreeAsync(ws, st), "workspace free");
   return CKKS_OK;
 }
 

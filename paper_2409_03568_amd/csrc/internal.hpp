@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -117,6 +118,14 @@ CKKS_SEG_HD inline uint32_t segment_of(const uint64_t *seg_end, uint32_t n_seg, 
 
 }  // namespace ckks
 
+// The per-call scratch buffer of one stream (see ckks::WsLease).
+struct StreamWorkspace {
+  hipStream_t stream = nullptr;
+  void *ptr = nullptr;
+  uint64_t bytes = 0;
+  hipEvent_t last = nullptr;  // recorded after the last call that used ptr
+};
+
 struct ckks_ctx {
   int device = 0;
   ckks::host::Resolved prm;
@@ -145,6 +154,8 @@ struct ckks_ctx {
   int num_cus = 1;              // compute units of the device (bounded, co-resident grids)
   hipStream_t aux = nullptr;    // second stream of cached encryption (misses beside the hit gather)
   void *noalloc_scratch = nullptr;  // this device's fixed scratch array (ckks_encrypt_cached_noalloc)
+  std::mutex ws_mu;                 // guards ws for the whole of a call that uses it
+  std::vector<StreamWorkspace> ws;  // per-call scratch, one buffer per stream
 };
 
 
@@ -200,6 +211,33 @@ struct TraceRange {
 
 // Records a message for ckks_last_error() (thread-local) and returns `code`.
 int api_fail(int code, const char *fmt, ...);
+
+// Per-call device scratch (cache metadata, product scratch, tile buffers): the context
+// keeps one buffer per stream, grown when a call needs more, and calls on a stream reuse
+// it in stream order.  The lease holds the context's workspace lock for the call (the
+// enqueue only) and records the buffer's event when the call returns, which orders the
+// buffer's next use after this call's work even if a different stream gets the same
+// handle later.  Growth waits for the old buffer's last use before freeing it.  (Scratch
+// from a stream-ordered pool, freed after each call, made the next call on the same
+// stream wait on the host until the device had reached that free.)
+class WsLease {
+ public:
+  WsLease(ckks_ctx *c, hipStream_t st) : c_(c), st_(st), lk_(c->ws_mu) {}
+  ~WsLease() {
+    if (w_) (void)hipEventRecord(w_->last, st_);
+  }
+  hipError_t get(uint64_t bytes, void **out);
+  WsLease(const WsLease &) = delete;
+  WsLease &operator=(const WsLease &) = delete;
+
+ private:
+  ckks_ctx *c_;
+  hipStream_t st_;
+  std::unique_lock<std::mutex> lk_;
+  StreamWorkspace *w_ = nullptr;
+};
+// Frees every stream's scratch buffer (the device must be idle).
+void ws_free_all(ckks_ctx *c);
 
 // Mean-filter multiplier: 1/k^2 as rint(q_{level-1} / k^2) per limb, and the scale after it.
 int filter_multiplier(const ckks_ctx *c, uint32_t level, double scale, uint32_t k, std::vector<uint64_t> &K,

@@ -319,3 +319,44 @@ def test_mul_level1_bitexact(P, oracle_mod, W):
     for i in range(px.size):
         assert np.array_equal(g[i], o.mul(A[i], B[i], level=1)), i
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# per-call scratch: calls queued back to back on one stream do not wait on the host, and
+# their results equal the same calls run one at a time (also across two streams)
+# ---------------------------------------------------------------------------
+def test_queued_cached_calls_do_not_block(P, c1, W):
+    import time
+
+    import torch
+
+    ctx, o = c1
+    _say("[gpu] queued cached encryptions")
+    big = _dev(W.uniform_image(71, 256, 256))  # 65,536 pixels: several ms of plain encryption
+    px = _dev(W.zipf_image(72, 64, 64))
+    radix = ctx.cache_build(P.CKKS_CACHE_RADIX, base=16, digits=2, seed=(7, 7))
+    value = ctx.cache_build(P.CKKS_CACHE_VALUE_TOPK, topk=32, zero_pool=8, scan_px=px, seed=(7, 7))
+    refs = []
+    for cache, seed in ((radix, (1, 1)), (value, (1, 2)), (radix, (1, 3))):
+        refs.append(_np(ctx.encrypt_cached(cache, px, seed)).copy())
+    st, st2 = torch.cuda.Stream(), torch.cuda.Stream()
+    hold = ctx.empty(big.numel())
+    outs = [ctx.empty(px.numel()) for _ in range(3)]
+    for cache in (radix, value):  # the stream's scratch reaches its size before the timed calls
+        ctx.encrypt_cached(cache, px, (5, 5), out=outs[0], stream=st)
+    torch.cuda.synchronize()
+    ctx.encrypt_pixels(big, (9, 9), out=hold, stream=st)  # keeps the stream busy
+    host_ms = []
+    for out, (cache, seed) in zip(outs[:2], ((radix, (1, 1)), (value, (1, 2)))):
+        t0 = time.perf_counter()
+        ctx.encrypt_cached(cache, px, seed, out=out, stream=st)
+        host_ms.append((time.perf_counter() - t0) * 1e3)
+    ctx.encrypt_cached(radix, px, (1, 3), out=outs[2], stream=st2)
+    torch.cuda.synchronize()
+    for got, ref in zip(outs, refs):
+        assert np.array_equal(_np(got), ref)
+    # the second call reuses the stream's scratch while the first is still queued: it must
+    # return without waiting for the device (the plain encryption alone takes ~10 ms)
+    assert host_ms[1] < 5.0, host_ms
+    radix.close()
+    value.close()
