@@ -94,3 +94,24 @@ def test_error_message_is_reported(pkg):
         pkg.ckks_params_resolve(pkg.ckks_params(10, 2, 36, 30))
     assert "log_n" in str(ei.value)
     assert "log_n" in pkg.ckks_last_error()
+
+
+def test_header_is_plain_c_and_cpp(tmp_path):
+    """The ABI header compiles on its own as strict C99 and as C++11 (no torch or HIP
+    types in the signatures)."""
+    import subprocess
+
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "ckks_mi355x.h"\n'
+                   "int main(void) {\n"
+                   "  ckks_params p;\n"
+                   "  ckks_ct_batch b;\n"
+                   "  (void)p; (void)b;\n"
+                   "  return ckks_ct_bytes(0, 1) == 0 ? 0 : 1;\n"
+                   "}\n")
+    inc = os.path.join(ROOT, "include")
+    for cmd in (["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only", "-I", inc, str(src)],
+                ["g++", "-std=c++11", "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only", "-x", "c++", "-I", inc,
+                 str(src)]):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
