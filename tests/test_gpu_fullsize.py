@@ -11,7 +11,9 @@ on outputs the oracle computes one by one:
   and a 5 x 5 filter in 64-row tiles on one stream: sampled outputs equal the oracle's
   window encryption, filter and decryption (within 1e-9);
 * one 384 x 384 serving job (the largest side of the serving mix) at N = 8192 with a full
-  value cache and a 3 x 3 filter: sampled outputs equal the oracle's (within 1e-9)."""
+  value cache and a 3 x 3 filter: sampled outputs equal the oracle's (within 1e-9);
+* the 256 x 256 step's radix- and value-cached encryptions: every ciphertext equals the
+  oracle's, residue by residue (plain encryption: every fourth)."""
 import sys
 
 import numpy as np
@@ -181,3 +183,66 @@ def test_serving_largest_job_sampled(mods, oracle_mod):
         assert abs(got[y, x] - val) < 1e-9, (y, x, got[y, x], val)
     cache.close()
     ctx.close()
+
+
+def test_c2_every_ciphertext(mods, oracle_mod):
+    """The 256 x 256 step's three encryptions at full size (N = 8192, 4 x 50-bit primes):
+    every one of the 65,536 ciphertexts of radix-cached (base 16, 2 digits) and
+    value-cached (top 64, pool 256) encryption, and every fourth of plain encryption (the
+    oracle's full encryptions take about a minute for all of them), equals the oracle's,
+    residue by residue (compared in chunks, the oracle on all host threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    P, W = mods
+    c = W.CONFIGS[2]
+    e = c.extras
+    img = W.config_image(2).reshape(-1)
+    n = img.size
+    _say("[gpu] full-size step: every ciphertext of %d pixels, three encryptions" % n)
+    ctx = P.Context(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    ctx.keygen(W.keygen_seed(2))
+    cseed, job = W.cache_seed(2), W.job_seed(2)
+    px = torch.from_numpy(img).cuda()
+    radix = ctx.cache_build(P.CKKS_CACHE_RADIX, base=e["base"], digits=e["digits"], seed=cseed)
+    value = ctx.cache_build(P.CKKS_CACHE_VALUE_TOPK, topk=e["topk"], zero_pool=e["pool"], scan_px=px, seed=cseed)
+    o = oracle_mod.Oracle(c.log_n, c.num_primes, c.prime_bits, c.log_scale)
+    o.keygen(W.keygen_seed(2))
+    rent = o.radix_entries(e["base"], e["digits"], cseed)
+    top = o.topk(o.histogram(img), e["topk"])
+    pool_ex = ThreadPoolExecutor(max_workers=oracle_mod.num_threads())
+    ventries = dict(zip(top, pool_ex.map(lambda v: o.value_entry(v, cseed), top)))
+    pool = np.stack(list(pool_ex.map(lambda u: o.pool_entry(u, cseed), range(e["pool"]))))
+    ct = ctx.empty(n)
+    chunk = 2048
+    for name in ("plain", "radix", "value"):
+        if name == "plain":
+            ctx.encrypt_pixels(px, job, out=ct)
+        else:
+            ctx.encrypt_cached(radix if name == "radix" else value, px, job, out=ct)
+        torch.cuda.synchronize()
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            got = ct.data[a:b].cpu().numpy().view(np.uint64).reshape(b - a, -1)
+            if name == "plain":  # every fourth index of the chunk
+                got = got[::4]
+                ref = np.stack(list(pool_ex.map(lambda t: o.encrypt(int(img[t]), job, t), range(a, b, 4))))
+            elif name == "radix":
+                ref = np.stack(list(pool_ex.map(
+                    lambda t: o.radix_encrypt(rent, e["base"], e["digits"], int(img[t]), job, t), range(a, b))))
+            else:
+                ref = np.stack(list(pool_ex.map(
+                    lambda t: o.value_encrypt(ventries.get(int(img[t])), pool, e["pool"], int(img[t]), job, t),
+                    range(a, b))))
+            if not np.array_equal(got, ref):
+                step = 4 if name == "plain" else 1
+                bad = [a + step * i for i in range(len(ref)) if not np.array_equal(got[i], ref[i])]
+                raise AssertionError("%s: ciphertexts differing from the oracle: %s" % (name, bad[:10]))
+        _say("[gpu]   %s: %d ciphertexts equal the oracle's" % (name, n // 4 if name == "plain" else n))
+    pool_ex.shutdown()
+    radix.close()
+    value.close()
+    ctx.close()
+    del px, ct
+    torch.cuda.empty_cache()
