@@ -68,6 +68,11 @@ constexpr double kFwdLimit = 4222124650659840.0;  // 2^52 - 2^48
 constexpr double kInvLimit = 2251799813685248.0;  // 2^51
 constexpr double kTwoPowMinus53 = 1.0 / 9007199254740992.0;
 
+// Flag bit of a forward schedule (above every stage bit): the transform's inputs are
+// integers in {-1, 0, 1}, so each first-stage product W*Y is an exact double (|W| <= q/2)
+// and needs no modular reduction.
+constexpr uint32_t kFwdTernaryInput = 1u << 31;
+
 struct FwdPlan {
   uint32_t mask;  // reduce after stage s when bit s is set
   double bound;   // bound on the outputs
@@ -115,7 +120,7 @@ struct Schedule {
   static constexpr double qmax = kClassQmax[RC];
   static constexpr FwdPlan small = forward_schedule(LOGN, qmax, 1.0);
   static constexpr FwdPlan big = forward_schedule(LOGN, qmax, qmax);
-  static constexpr uint32_t fwd_small = small.mask;
+  static constexpr uint32_t fwd_small = small.mask | kFwdTernaryInput;
   static constexpr uint32_t fwd_big = big.mask;
   static constexpr double inv_input =
       pointwise_bound(qmax, small.bound > big.bound ? small.bound : big.bound);
@@ -267,7 +272,13 @@ CKKS_HD void fwd_pass(double (&x)[1 << LOGR], int tid_in, const double *__restri
           W = regs.w[u * PT::PER + (1 << l) - 1 + t];
         else
           W = ld_table(tw, (1u << s) + (blk << l) + t);
-        ct_butterfly(x[k * G + u], x[(k + half) * G + u], W, q, qinv);
+        if (s == 0 && (RED & kFwdTernaryInput)) {
+          const double t = x[(k + half) * G + u] * W;  // exact: |Y| <= 1
+          x[(k + half) * G + u] = x[k * G + u] - t;
+          x[k * G + u] = x[k * G + u] + t;
+        } else {
+          ct_butterfly(x[k * G + u], x[(k + half) * G + u], W, q, qinv);
+        }
       }
       if ((RED >> s) & 1u) {
 #pragma unroll
