@@ -240,7 +240,8 @@ int ckks_cache_import(ckks_ctx *ctx, const ckks_cache_desc *desc, uint32_t n_ent
  *  VALUE_* (Sec. 3.2 + 3.3): a cached value p gives c = Enc(p) + Z_u with
  *    u = floor(zero_pool * w / 2^64), w = auxiliary word 0; a value that is not
  *    cached is encrypted in full exactly like ckks_encrypt_pixels.
- * Output as for ckks_encrypt_pixels.  Uses temporary device memory (stream-ordered). */
+ * Output as for ckks_encrypt_pixels.  Its per-pixel metadata goes to a scratch buffer
+ * that the context keeps for this stream (see "Per-stream scratch" below). */
 int ckks_encrypt_cached(ckks_ctx *ctx, const ckks_cache *cache, const uint8_t *d_px, uint64_t n,
                         const uint64_t seed[2], uint64_t first_index, ckks_ct_batch *out, void *stream);
 
@@ -276,8 +277,18 @@ int ckks_sub(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks
  * out->scale = a->scale * b->scale at the same level (ckks_rescale brings it back).
  * Requires ckks_relin_keygen (CKKS_ESTATE).  out->data may equal a->data or b->data;
  * any other overlap is CKKS_EINVAL.  Uses min(count, 2048) * (2 level + 2) * N * 8
- * bytes of temporary device memory (stream-ordered). */
+ * bytes of scratch that the context keeps for this stream (see "Per-stream scratch"
+ * below). */
 int ckks_mul(ckks_ctx *ctx, const ckks_ct_batch *a, const ckks_ct_batch *b, ckks_ct_batch *out, void *stream);
+
+/* Per-stream scratch (ckks_encrypt_cached, ckks_mul): the context keeps one device buffer
+ * for each stream these calls were given, so that calls queued on a stream reuse it
+ * without waiting on the host.  A buffer grows (by 1.5x, in 2 MiB steps) when a call
+ * needs more; growing first waits on the host for that stream's previous use.  Buffers
+ * of at most 16 streams are kept: a call on a further stream first releases the least
+ * recently used one, after waiting on the host for its last use.  All are freed by
+ * ckks_context_destroy.  Calls that enqueue on one context are serialized on the host
+ * for the short time they enqueue. */
 
 /* out = c * a.  An integer-valued c multiplies exactly and keeps the scale; any other c
  * multiplies by K = rint(c * q_{level-1}) and sets out->scale = a->scale * q_{level-1}, so

@@ -264,7 +264,20 @@ bool limb0_decode_exact(const ckks_ctx *c, double value_bound, double terms, boo
 hipError_t WsLease::get(uint64_t bytes, void **out) {
   size_t i = 0;
   while (i < c_->ws.size() && c_->ws[i].stream != st_) i++;
-  if (i == c_->ws.size()) {
+  if (i == c_->ws.size() && c_->ws.size() >= kMaxStreamWs) {
+    // release the least recently used stream's buffer once its last use is done, and
+    // give its entry (and event) to this stream
+    i = 0;
+    for (size_t j = 1; j < c_->ws.size(); j++)
+      if (c_->ws[j].used < c_->ws[i].used) i = j;
+    StreamWorkspace &old = c_->ws[i];
+    hipError_t e = hipEventSynchronize(old.last);
+    if (e == hipSuccess && old.ptr) e = hipFree(old.ptr);
+    old.ptr = nullptr;
+    old.bytes = 0;
+    if (e != hipSuccess) return e;
+    old.stream = st_;
+  } else if (i == c_->ws.size()) {
     StreamWorkspace w;
     w.stream = st_;
     const hipError_t e = hipEventCreateWithFlags(&w.last, hipEventDisableTiming);
@@ -272,6 +285,7 @@ hipError_t WsLease::get(uint64_t bytes, void **out) {
     c_->ws.push_back(w);
   }
   StreamWorkspace &w = c_->ws[i];
+  w.used = ++c_->ws_leases;
   if (w.bytes < bytes) {
     if (w.ptr) {
       hipError_t e = hipEventSynchronize(w.last);

@@ -17,6 +17,9 @@ namespace ckks {
 
 constexpr int kMaxL = 16;
 constexpr int kMaxDigits = 8;
+// Streams whose per-call scratch buffer a context keeps at once (least recently used
+// released first).
+constexpr size_t kMaxStreamWs = 16;
 
 // Per-limb constants; kernels read the device copy held by the context.  Index L holds
 // the special prime of key switching (when the context has one).
@@ -124,6 +127,7 @@ struct StreamWorkspace {
   void *ptr = nullptr;
   uint64_t bytes = 0;
   hipEvent_t last = nullptr;  // recorded after the last call that used ptr
+  uint64_t used = 0;          // the context's lease count at the last use (for eviction)
 };
 
 struct ckks_ctx {
@@ -155,7 +159,8 @@ struct ckks_ctx {
   hipStream_t aux = nullptr;    // second stream of cached encryption (misses beside the hit gather)
   void *noalloc_scratch = nullptr;  // this device's fixed scratch array (ckks_encrypt_cached_noalloc)
   std::mutex ws_mu;                 // guards ws for the whole of a call that uses it
-  std::vector<StreamWorkspace> ws;  // per-call scratch, one buffer per stream
+  std::vector<StreamWorkspace> ws;  // per-call scratch, one buffer per stream (at most kMaxStreamWs)
+  uint64_t ws_leases = 0;           // leases taken so far (orders the buffers by last use)
 };
 
 

@@ -360,3 +360,36 @@ def test_queued_cached_calls_do_not_block(P, c1, W):
     assert host_ms[1] < 5.0, host_ms
     radix.close()
     value.close()
+
+
+def test_scratch_of_many_streams(P, c1, W):
+    """Cached encryptions and products on more streams than the context keeps scratch
+    buffers for (16): each further stream takes over the least recently used buffer, and
+    every result stays bit-exact, also with the calls of all streams queued at once."""
+    import torch
+
+    ctx, o = c1
+    _say("[gpu] cached encryption and products on 24 streams")
+    px = _dev(W.zipf_image(73, 32, 32))
+    value = ctx.cache_build(P.CKKS_CACHE_VALUE_TOPK, topk=16, zero_pool=8, scan_px=px, seed=(3, 3))
+    refs = [_np(ctx.encrypt_cached(value, px, (2, k))).copy() for k in range(24)]
+    streams = [torch.cuda.Stream() for _ in range(24)]
+    outs = [ctx.empty(px.numel()) for _ in range(24)]
+    for rnd in range(2):  # the second round finds every buffer taken over by another stream
+        for k, st in enumerate(streams):
+            ctx.encrypt_cached(value, px, (2, k), out=outs[k], stream=st)
+        torch.cuda.synchronize()
+        for k in range(24):
+            assert np.array_equal(_np(outs[k]), refs[k]), (rnd, k)
+    ctx.relin_keygen((5, 6))
+    a = ctx.encrypt_pixels(px, (4, 1))
+    b = ctx.encrypt_pixels(px, (4, 2))
+    ref = _np(ctx.mul(a, b)).copy()
+    prods = [ctx.empty(px.numel()) for _ in range(20)]
+    for k in range(20):
+        with torch.cuda.stream(streams[k]):
+            ctx.mul(a, b, out=prods[k], stream=streams[k])
+    torch.cuda.synchronize()
+    for k in range(20):
+        assert np.array_equal(_np(prods[k]), ref), k
+    value.close()
