@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <unistd.h>
 
+#include <atomic>
 #include <fstream>
 #include <sstream>
 #include <vector>
@@ -76,6 +77,7 @@ bool valid(const Values &v, int log_n) {
 }
 
 static int read_lines(const char *path, std::vector<std::string> *lines, bool *exists) {
+  errno = 0;
   std::ifstream f(path);
   *exists = false;
   if (!f) {
@@ -102,7 +104,10 @@ int store(const char *path, const Key &k, const Values &v) {
     keep.push_back(l);
   }
   keep.push_back(format_line(k, v));
-  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+  // a temporary name of this process and call, so concurrent stores never share one
+  static std::atomic<unsigned> serial{0};
+  const std::string tmp =
+      std::string(path) + ".tmp" + std::to_string((long)getpid()) + "." + std::to_string(serial.fetch_add(1));
   FILE *f = fopen(tmp.c_str(), "w");
   if (!f) return errno ? errno : EIO;
   bool ok = true;
