@@ -2,6 +2,8 @@
 // on canonical uint64 residues.  All of these are bound by HBM bandwidth: each kernel
 // streams its ciphertexts once with 16-byte accesses, one workgroup per N-coefficient
 // row ([ct][poly][limb] rows), and keeps the per-limb constants in registers.
+#include <atomic>
+
 #include "internal.hpp"
 #include "modarith.hpp"
 #include "philox.hpp"
@@ -135,45 +137,89 @@ struct FilterConsts {
 };
 
 constexpr int kFilterWaves = 8;
+// s_waitcnt immediate that waits for every outstanding vector memory operation of the wave
+// (vmcnt 0; expcnt and lgkmcnt at their maxima, i.e. not waited for)
+constexpr int kWaitVmcnt0 = 0x0F70;
+// cache-policy operand of a load: non-temporal
+constexpr int kCpolNonTemporal = 2;
 constexpr int kFilterThreads = 64 * kFilterWaves;
+
+// Columns of one image row that a workgroup stages in LDS (its 8 waves' output columns and
+// the halos on both sides), and the staging buffers' bytes (two rows, 64 coefficients).
+template <int KW, int LV, int XT>
+constexpr int filter_stage_cols() {
+  return kFilterWaves * XT + 2 * (KW / 2);
+}
+template <int KW, int LV, int XT>
+constexpr size_t filter_lds_bytes() {
+  return 2 * (size_t)filter_stage_cols<KW, LV, XT>() * LV * 64 * sizeof(double);
+}
 
 template <int KW, int LV, int XT>
 __global__ void __launch_bounds__(kFilterThreads)
     k_mean_filter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t H, uint32_t W, uint32_t y_begin,
                   uint32_t y_end, int log_n, uint32_t groups, FilterConsts fc) {
   constexpr int RAD = KW / 2, XC = XT + 2 * RAD;
+  constexpr int XW = filter_stage_cols<KW, LV, XT>(), NV = XW * LV;  // staged columns, 64-word vectors per row
+  static_assert(NV % 2 == 0, "a staging load moves two vectors");
   const int N = 1 << log_n;
   // logical workgroup lb = (64-coefficient chunk jc, poly, tile group g), g fastest; its
-  // wave w takes column tile kFilterWaves * g + w.  The tile groups of one (jc, poly) run
-  // side by side on one XCD and walk down the rows at about the same pace, so a halo
-  // column read by two neighbouring tiles is mostly served by that XCD's L2.
+  // wave w takes column tile kFilterWaves * g + w.  The workgroup stages each input row's
+  // columns (its waves' output columns and the halos) once in LDS, loaded straight from
+  // HBM into LDS with non-temporal loads one row ahead of use, and its waves read their
+  // columns from there: the image streams past the caches without displacing what other
+  // kernels keep in them (cache entries between calls), and the halo columns two waves
+  // share are read from HBM once.
+  extern __shared__ uint64_t stage[];  // [2][NV][64] residues: row buffers, alternating
   const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const uint32_t g = lb % groups;
   const uint32_t rest = lb / groups;
   const int poly = (int)(rest & 1);
-  const int j = (int)((rest >> 1) * 64 + (threadIdx.x & 63));
-  // a wave past the right edge reads clamped columns and writes nothing, but keeps to
-  // the workgroup's per-row barrier
-  const uint64_t x0 = ((uint64_t)g * kFilterWaves + (threadIdx.x >> 6)) * XT;
-  uint32_t xs[XC];
-#pragma unroll
-  for (int d = 0; d < XC; d++) {
-    const int64_t xx = (int64_t)x0 + d - RAD;
-    xs[d] = (uint32_t)(xx < 0 ? 0 : (xx >= (int64_t)W ? W - 1 : xx));
-  }
+  const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+  const uint64_t jc = (uint64_t)(rest >> 1) * 64;
+  // a wave past the right edge reads clamped columns and writes nothing, but takes part
+  // in the staging and the workgroup's barriers
+  const uint64_t xw0 = (uint64_t)g * kFilterWaves * XT;  // first output column of the workgroup
+  const uint64_t x0 = xw0 + (uint64_t)wv * XT;            // first output column of this wave
   const uint64_t ct_stride = (uint64_t)2 * LV * N;
-  const uint64_t base = (uint64_t)poly * LV * N + j;
-  // horizontal sums of input row yy for the XT output columns
-  auto hsum = [&](int64_t yy, double (&h)[XT][LV]) {
+  const uint64_t pbase = (uint64_t)poly * LV * N + jc;
+  const int64_t y_last = (int64_t)y_end - 1 + RAD;  // last input row the workgroup needs
+  // Loads input row yy into buffer b: vector v = (staged column v / LV, limb v % LV) is
+  // the 64 coefficients of that limb of image column xw0 + v / LV - RAD (clamped); each
+  // load instruction moves two vectors, 16 bytes per lane.
+  auto stage_row = [&](int64_t yy, int b) {
     const uint32_t yi = (uint32_t)(yy < 0 ? 0 : (yy >= (int64_t)H ? H - 1 : yy));
     const uint64_t y = yi < fc.ring ? yi : yi % fc.ring;
+    uint64_t *sb = stage + (size_t)b * NV * 64;
+    for (int pr = wv; pr < NV / 2; pr += kFilterWaves) {
+      const int v = 2 * pr + (lane >> 5);
+      const int col = v / LV, i = v % LV;
+      const int64_t xx = (int64_t)xw0 + col - RAD;
+      const uint64_t xc = (uint64_t)(xx < 0 ? 0 : (xx >= (int64_t)W ? (int64_t)W - 1 : xx));
+      const uint64_t *p = in + (y * W + xc) * ct_stride + pbase + (size_t)i * N + 2 * (lane & 31);
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)p,
+                                       (__attribute__((address_space(3))) void *)(sb + (size_t)pr * 128), 16, 0,
+                                       kCpolNonTemporal);
+    }
+  };
+  const uint64_t out_stride = (uint64_t)2 * (LV - 1) * N;
+  const uint64_t out_base = (uint64_t)poly * (LV - 1) * N + jc + lane;
+  int buf = 0;
+  stage_row((int64_t)y_begin - RAD, 0);
+  // horizontal sums of input row yy (staged in buffer buf) for the XT output columns
+  auto hsum = [&](int64_t yy, double (&h)[XT][LV]) {
+    // this wave's staging loads are complete (the wait also covers its output stores);
+    // after the barrier all waves' are, and every wave has finished reading the other buffer
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (yy + 1 <= y_last) stage_row(yy + 1, buf ^ 1);
+    const uint64_t *sb = stage + (size_t)buf * NV * 64;
     double c[XC][LV];
 #pragma unroll
-    for (int d = 0; d < XC; d++) {
-      const uint64_t *p = in + (y * W + xs[d]) * ct_stride + base;
+    for (int d = 0; d < XC; d++)
 #pragma unroll
-      for (int i = 0; i < LV; i++) c[d][i] = u64_to_f64(p[(size_t)i * N]);
-    }
+      for (int i = 0; i < LV; i++) c[d][i] = u64_to_f64(sb[((wv * XT + d) * LV + i) * 64 + lane]);
+    buf ^= 1;
 #pragma unroll
     for (int t = 0; t < XT; t++) {
 #pragma unroll
@@ -199,8 +245,6 @@ __global__ void __launch_bounds__(kFilterThreads)
 #pragma unroll
       for (int i = 0; i < LV; i++) v[t][i] += ring[d][t][i];
   }
-  const uint64_t out_stride = (uint64_t)2 * (LV - 1) * N;
-  const uint64_t out_base = (uint64_t)poly * (LV - 1) * N + j;
   const double ql = fc.q[LV - 1], qlinv = fc.qinv[LV - 1];
   for (uint32_t y0 = y_begin; y0 < y_end; y0 += KW) {
 #pragma unroll
@@ -231,11 +275,10 @@ __global__ void __launch_bounds__(kFilterThreads)
             ring[s][t][i] = nh[t][i];
           }
       }
-      // keep the waves of the workgroup on one row: the halo columns two neighbouring
-      // waves share are then read at about the same time and served by the cache
-      __syncthreads();
     }
   }
+  // no staging load may still be writing this workgroup's LDS when it ends
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,12 +353,27 @@ template <int KW, int LV>
 static hipError_t filter_t(const uint64_t *in, uint64_t *out, uint32_t H, uint32_t W, uint32_t y0, uint32_t y1,
                            int log_n, const FilterConsts &fc, hipStream_t st) {
   constexpr int XT = filter_xt<KW, LV>();
+  constexpr size_t lds = filter_lds_bytes<KW, LV, XT>();
+  static_assert(lds <= 160 * 1024, "staging buffers exceed a CU's LDS");
   const uint64_t tiles = ((uint64_t)W + XT - 1) / XT;
   const uint64_t groups = (tiles + kFilterWaves - 1) / kFilterWaves;
   const uint64_t blocks = groups * 2 * (((uint64_t)1 << log_n) / 64);
   if (blocks > 0xffffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_mean_filter<KW, LV, XT>), dim3((uint32_t)blocks), dim3(kFilterThreads), 0, st, in, out, H, W,
-                     y0, y1, log_n, (uint32_t)groups, fc);
+  if constexpr (lds > 64 * 1024) {
+    // once per kernel and device (also keeps the call out of graph captures after the first launch)
+    static std::atomic<uint64_t> done{0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 63;
+    const uint64_t bit = 1ull << dev;
+    if (!(done.load(std::memory_order_acquire) & bit)) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_mean_filter<KW, LV, XT>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      done.fetch_or(bit, std::memory_order_acq_rel);
+    }
+  }
+  hipLaunchKernelGGL((k_mean_filter<KW, LV, XT>), dim3((uint32_t)blocks), dim3(kFilterThreads), lds, st, in, out, H,
+                     W, y0, y1, log_n, (uint32_t)groups, fc);
   return hipGetLastError();
 }
 
