@@ -329,6 +329,24 @@ def test_mean_filter_ragged_shape(c1, W):
     assert np.max(np.abs(dec - _box(img, 3))) < 1e-3
 
 
+@pytest.mark.parametrize("H,Wd,k", [(1, 1, 3), (1, 37, 3), (37, 1, 5), (3, 37, 5), (2, 17, 3), (5, 33, 7)])
+def test_mean_filter_degenerate_and_multi_group_shapes(c1, W, H, Wd, k):
+    """Single rows and columns (every window clamped), and widths past one workgroup's 16
+    output columns with a ragged last group: every output equals the oracle's."""
+    ctx, o = c1
+    _say("[gpu] mean filter %dx%d k=%d" % (H, Wd, k))
+    img = W.uniform_image(40 + H + Wd, H, Wd)
+    cts = ctx.encrypt_pixels(_dev(img), W.job_seed(1))
+    out = ctx.mean_filter(cts, H, Wd, k)
+    g, allc = _np(out), _np(cts)
+    for y in range(H):
+        for x in range(Wd):
+            ref, _ = o.mean_filter_pixel(allc, H, Wd, k, y, x)
+            assert np.array_equal(g[y * Wd + x], ref), (y, x)
+    dec = ctx.decrypt_pixels(out).cpu().numpy().reshape(H, Wd)
+    assert np.max(np.abs(dec - _box(img, k))) < 1e-3
+
+
 @pytest.mark.slow
 def test_mean_filter_c2_full_size_sampled(c2, W):
     ctx, o = c2
